@@ -1,0 +1,190 @@
+/*
+ * tucker.h -- C ABI of the MI355X (gfx950) Tucker-ALS / HOOI library.
+ *
+ * What is computed (Sharma & Grover, arXiv 2104.04726, Sec. III-B):
+ *   Given an order-N tensor X (s_1 x ... x s_N) and ranks R_n, find a core G
+ *   (R_1 x ... x R_N) and factors U_n (s_n x R_n, orthonormal columns) with
+ *   X ~ G x_1 U_1 ... x_N U_N                                  (eq. (1)-(2)),
+ *   starting from the truncated HOSVD                          (Sec. III-B.1, eq. (3)-(7))
+ *   and refining by ALS sweeps (HOOI): for n = 1..N,
+ *   Y = X x_{m != n} U_m^T, U_n <- leading R_n eigenvectors of Y_(n) Y_(n)^T
+ *                                                              (eq. (8) and the text after it).
+ *
+ * Conventions shared by every entry point:
+ *   - All tensors and matrices are dense, row-major (C order): mode 1 varies slowest.
+ *     U_n is s_n x R_n row-major, the core is R_1 x ... x R_N row-major.
+ *   - Pointers documented as "device" point to GPU memory on the context's device;
+ *     they are owned by the caller, and inputs are only read.  Pointers documented as
+ *     "host" are ordinary CPU memory.
+ *   - Work is enqueued on the context's stream (tucker_options.stream; NULL = the device's
+ *     default (null) stream).  Functions that return host values (fit, sweeps) synchronise that
+ *     stream before returning; the others are stream-ordered and return immediately.
+ *   - Every function returns a tucker_status.  Arguments are validated on the host before
+ *     any device work; TUCKER_ERR_INVALID_ARG leaves all outputs untouched.  After any
+ *     other error the outputs are unspecified and tucker_last_error() describes the cause.
+ *   - A context is not thread-safe: use one per thread.
+ */
+#ifndef TUCKER_MI355X_H
+#define TUCKER_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TUCKER_MAX_ORDER 8
+
+/* Opaque context: owns a device workspace, a stream binding and the last statistics. */
+typedef struct tucker_ctx tucker_ctx;
+
+typedef enum {
+    TUCKER_OK = 0,
+    TUCKER_ERR_INVALID_ARG = 1,   /* argument rejected by host-side validation            */
+    TUCKER_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or exceeds hbm_budget_bytes */
+    TUCKER_ERR_DEVICE = 3,        /* no usable GPU, or a HIP runtime error                */
+    TUCKER_ERR_NUMERICAL = 4,     /* non-finite input norm, or an unrecoverable breakdown */
+    TUCKER_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement        */
+} tucker_status;
+
+/* Operand precision of the TTM and Gram contractions (accumulation is always FP32; the
+ * orthogonalisation and the norms are FP64 whatever the choice). */
+typedef enum {
+    TUCKER_FP32 = 0,
+    TUCKER_BF16 = 1,
+    TUCKER_FP16 = 2,
+    TUCKER_FP8_E4M3 = 3
+} tucker_precision;
+
+typedef struct {
+    int device;                  /* HIP device ordinal                                        */
+    void* stream;                /* hipStream_t owned by the caller; NULL = default stream    */
+    tucker_precision precision;  /* contraction operand precision of the sweeps               */
+    int refine_sweeps;           /* FP32 sweeps appended after reduced-precision sweeps       */
+    int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1)   */
+    int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD     */
+    double inner_tol;            /* reserved (0)                                              */
+    int use_graphs;              /* reserved (0)                                              */
+    size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
+    uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
+} tucker_options;
+
+/* Statistics of the last tucker_decompose* call on a context (host values). */
+typedef struct {
+    double init_ms;              /* T-HOSVD initialisation, GPU time                          */
+    double sweeps_ms;            /* all ALS sweeps, GPU time                                  */
+    double final_fit_ms;         /* exact-residual fit and output copies, GPU time            */
+    double fit_gram;             /* last fit from ||X||^2 - ||G||^2 (cheap, FP32 core)        */
+    int sweeps;                  /* sweeps performed                                          */
+    int chol_shifts;             /* Cholesky pivots that needed the shifted fallback          */
+    size_t workspace_bytes;      /* device workspace held by the context                      */
+} tucker_stats;
+
+/* Fills *o with the defaults: device 0, default stream, FP32, refine_sweeps 1,
+ * inner_iters 1, init_iters 20, seed 0x5eed. */
+void tucker_default_options(tucker_options* o);
+
+/* Host-only validation of a decomposition request (no GPU needed).  Rules:
+ * 2 <= ndim <= 8; dims[n] >= 1; 1 <= ranks[n] <= dims[n]; ranks[n] <= prod_{m != n} ranks[m]
+ * (otherwise the Gram of Y_(n) has rank < R_n and its leading subspace is not determined);
+ * max_iters >= 0; tol >= 0 and not NaN.  dims/ranks: host arrays of ndim entries. */
+tucker_status tucker_validate(int ndim, const int64_t* dims, const int64_t* ranks,
+                              int max_iters, double tol);
+
+/* Host-only: device workspace (bytes) a decomposition of this shape needs. */
+tucker_status tucker_workspace_size(int ndim, const int64_t* dims, const int64_t* ranks,
+                                    tucker_precision precision, size_t* bytes);
+
+/* Creates a context on opts->device (opts may be NULL for the defaults).  Returns
+ * TUCKER_ERR_DEVICE when no GPU is usable.  *out receives the context (caller destroys). */
+tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out);
+
+/* Frees the context's workspace and stream.  NULL is accepted. */
+tucker_status tucker_destroy(tucker_ctx* ctx);
+
+/* Tucker decomposition by HOOI (T-HOSVD start, then up to max_iters sweeps).
+ *   tensor   device, prod(dims) floats, read-only.
+ *   dims     host, ndim entries; ranks host, ndim entries.
+ *   max_iters number of sweeps; 0 returns the T-HOSVD result.
+ *   tol      stop early when |fit_k - fit_{k-1}| < tol (tol = 0: run all sweeps).
+ *   core     device, prod(ranks) floats (output).
+ *   factors  host array of ndim device pointers; factors[n] receives dims[n]*ranks[n] floats.
+ *   fit      host, receives 1 - ||X - Xhat|| / ||X|| (evaluated from the explicit residual).
+ *   sweeps_done host, nullable.
+ * Blocks until the outputs are complete.  ||X|| = 0 gives fit 1, a zero core and the leading
+ * columns of the identity as factors; a non-finite ||X||^2 gives TUCKER_ERR_NUMERICAL. */
+tucker_status tucker_decompose(tucker_ctx* ctx, const float* tensor, int ndim,
+                               const int64_t* dims, const int64_t* ranks,
+                               int max_iters, double tol,
+                               float* core, float* const* factors,
+                               double* fit, int* sweeps_done);
+
+/* As tucker_decompose, plus:
+ *   init_factors host array of ndim device pointers (nullable): orthonormal s_n x R_n starting
+ *                factors used instead of the T-HOSVD (resume / refinement).
+ *   fit_history  host, nullable, max_iters + 1 doubles: fit_0 (start) and the fit after each
+ *                sweep from ||X||^2 - ||G||^2; entries past sweeps_done are left untouched. */
+tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim,
+                                  const int64_t* dims, const int64_t* ranks,
+                                  int max_iters, double tol,
+                                  const float* const* init_factors,
+                                  float* core, float* const* factors, double* fit,
+                                  double* fit_history, int* sweeps_done);
+
+/* Xhat = G x_1 U_1 ... x_N U_N (eq. (1)).  core device prod(ranks) floats; factors host array
+ * of device pointers (s_n x R_n); out device prod(dims) floats.  Stream-ordered. */
+tucker_status tucker_reconstruct(tucker_ctx* ctx, const float* core, const float* const* factors,
+                                 int ndim, const int64_t* dims, const int64_t* ranks, float* out);
+
+/* ---- Step-level entry points (the building blocks of a sweep, exposed for testing) ---- */
+
+/* Mode-n product with a transposed factor (eq. (8)): out = in x_mode U^T.
+ * in device prod(dims) floats; U device dims[mode] x r floats (row-major);
+ * out device, dims with dims[mode] replaced by r.  Stream-ordered. */
+tucker_status tucker_ttm(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims,
+                         int mode, const float* U, int64_t r, float* out);
+
+/* Mode-n Gram matrix in_(mode) in_(mode)^T (the text after eq. (8)).
+ * out device dims[mode]^2 floats, symmetric, row-major.  Stream-ordered. */
+tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims,
+                          int mode, float* out);
+
+/* Orthonormal basis of the column space of Z (rows x cols, rows >= cols) by FP64
+ * CholeskyQR2 with column scaling.  Z, Q device floats, row-major; Q may alias Z.
+ * Stream-ordered. */
+tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols,
+                                    float* Q);
+
+/* The two halves of one CholeskyQR pass, exposed separately:
+ *   tucker_gram_tn64: W = Z^T Z accumulated in FP64.  Z device rows x cols floats (row-major);
+ *                     W device cols x cols doubles.
+ *   tucker_chol_inv:  for symmetric positive definite W (n x n doubles, device, read-only),
+ *                     D = diag(W)^(1/2), D^-1 W D^-1 = L L^T, writes T = L^-1 D^-1 (lower triangular,
+ *                     upper part zero) to T (device n x n doubles); Z T^T then has orthonormal
+ *                     columns.  Pivots that are not safely positive are shifted and counted in
+ *                     tucker_stats.chol_shifts.
+ * Both stream-ordered. */
+tucker_status tucker_gram_tn64(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols, double* W);
+tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, double* T);
+
+/* Leading r eigenvectors (descending eigenvalues) of a symmetric n x n matrix, n <= 64,
+ * by cyclic Jacobi in FP64.  S device n*n floats; U device n*r floats; lam device n doubles
+ * (all eigenvalues, descending; nullable).  Stream-ordered. */
+tucker_status tucker_sym_eig(tucker_ctx* ctx, const float* S, int64_t n, int64_t r,
+                             float* U, double* lam);
+
+/* Sum of squares of n floats accumulated in FP64 (two-stage, deterministic).
+ * x device; result host.  Synchronises. */
+tucker_status tucker_sumsq(tucker_ctx* ctx, const float* x, int64_t n, double* result);
+
+/* ---- Diagnostics ---- */
+const char* tucker_status_string(tucker_status s);
+const char* tucker_last_error(const tucker_ctx* ctx);   /* never NULL; "" when none */
+tucker_status tucker_get_stats(const tucker_ctx* ctx, tucker_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKER_MI355X_H */

@@ -1,0 +1,254 @@
+"""Tucker-ALS (HOOI) on MI355X: Python binding of libtucker_mi355x.so.
+
+Argument marshalling only: every step of the decomposition runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  Sec. III-B of arXiv 2104.04726
+defines the computation:
+
+    X ~ G x_1 U_1 ... x_N U_N,   T-HOSVD start, HOOI sweeps via mode-n Gram eigenvectors.
+
+Example::
+
+    import torch, paper_2104_04726_amd as tk
+    x = torch.randn(64, 48, 3, 6, device="cuda")
+    res = tk.decompose(x, ranks=(16, 12, 3, 4), max_iters=10)
+    xhat = tk.reconstruct(res.core, res.factors)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+from . import _lib
+from ._lib import FP32, BF16, FP16, FP8_E4M3  # noqa: F401
+
+__all__ = ["Context", "TuckerError", "Result", "decompose", "reconstruct", "default_context", "validate",
+           "workspace_size"]
+
+_PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        self.code = int(code)
+        super().__init__(f"{_lib.status_name(code)}: {message}")
+
+
+@dataclass
+class Result:
+    core: "object"                  # torch.Tensor (R_1, ..., R_N), float32, on the device
+    factors: List["object"]         # torch.Tensor (s_n, R_n), float32, orthonormal columns
+    fit: float                      # 1 - ||X - Xhat|| / ||X|| from the explicit residual
+    fit_history: List[float] = field(default_factory=list)   # fit_0 .. fit_sweeps (||G||-based)
+    sweeps: int = 0
+    stats: dict = field(default_factory=dict)
+
+
+def _check(code: int, ctx=None):
+    if code != _lib.OK:
+        msg = ""
+        if ctx is not None:
+            raw = _lib.lib().tucker_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        raise TuckerError(code, msg)
+
+
+def _f32_device(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return t.contiguous()
+
+
+def validate(dims: Sequence[int], ranks: Sequence[int], max_iters: int = 0, tol: float = 0.0) -> int:
+    """Host-only validation; returns the status code (0 = ok)."""
+    n = len(dims)
+    if len(ranks) != n:
+        return _lib.ERR_INVALID_ARG
+    return int(_lib.lib().tucker_validate(n, _lib.i64(dims), _lib.i64(ranks), int(max_iters), float(tol)))
+
+
+def workspace_size(dims: Sequence[int], ranks: Sequence[int], precision: str = "fp32") -> int:
+    out = C.c_size_t(0)
+    _check(_lib.lib().tucker_workspace_size(len(dims), _lib.i64(dims), _lib.i64(ranks),
+                                            _PRECISIONS[precision], C.byref(out)))
+    return int(out.value)
+
+
+class Context:
+    """A library context bound to one device and one stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None, inner_iters: int = 1, init_iters: int = 20,
+                 seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
+                 refine_sweeps: int = 1):
+        import torch
+        lib = _lib.lib()
+        opts = _lib.Options()
+        lib.tucker_default_options(C.byref(opts))
+        opts.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.torch_stream = stream
+        opts.stream = C.c_void_p(int(stream.cuda_stream)) if hasattr(stream, "cuda_stream") else C.c_void_p(stream)
+        opts.inner_iters = int(inner_iters)
+        opts.init_iters = int(init_iters)
+        opts.seed = int(seed)
+        opts.hbm_budget_bytes = int(hbm_budget_bytes)
+        opts.precision = _PRECISIONS[precision]
+        opts.refine_sweeps = int(refine_sweeps)
+        self.device = int(device)
+        self._h = C.c_void_p()
+        _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _lib.lib().tucker_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- decomposition
+    def decompose(self, x, ranks: Sequence[int], max_iters: int = 10, tol: float = 0.0,
+                  init_factors: Optional[Sequence] = None) -> Result:
+        import torch
+        x = _f32_device(x, "x")
+        dims = list(x.shape)
+        ranks = [int(r) for r in ranks]
+        n = len(dims)
+        if len(ranks) != n:
+            raise TuckerError(_lib.ERR_INVALID_ARG, "len(ranks) != x.dim()")
+        dev = x.device
+        core = torch.empty(ranks, dtype=torch.float32, device=dev)
+        factors = [torch.empty((dims[i], ranks[i]), dtype=torch.float32, device=dev) for i in range(n)]
+        fptrs = (C.c_void_p * n)(*[f.data_ptr() for f in factors])
+        iptrs = None
+        keep = []
+        if init_factors is not None:
+            init = [_f32_device(u, "init_factors") for u in init_factors]
+            keep = init
+            iptrs = (C.c_void_p * n)(*[u.data_ptr() for u in init])
+        fit = C.c_double(0.0)
+        hist = (C.c_double * (max_iters + 1))()
+        sweeps = C.c_int(0)
+        code = _lib.lib().tucker_decompose_ex(
+            self._h, C.c_void_p(x.data_ptr()), n, _lib.i64(dims), _lib.i64(ranks), int(max_iters), float(tol),
+            iptrs, C.c_void_p(core.data_ptr()), fptrs, C.byref(fit), hist, C.byref(sweeps))
+        del keep
+        _check(code, self._h)
+        return Result(core, factors, float(fit.value), [float(hist[i]) for i in range(sweeps.value + 1)],
+                      int(sweeps.value), self.stats())
+
+    def reconstruct(self, core, factors):
+        import torch
+        core = _f32_device(core, "core")
+        factors = [_f32_device(u, "factor") for u in factors]
+        dims = [int(u.shape[0]) for u in factors]
+        ranks = list(core.shape)
+        out = torch.empty(dims, dtype=torch.float32, device=core.device)
+        fptrs = (C.c_void_p * len(factors))(*[u.data_ptr() for u in factors])
+        _check(_lib.lib().tucker_reconstruct(self._h, C.c_void_p(core.data_ptr()), fptrs, len(dims),
+                                             _lib.i64(dims), _lib.i64(ranks), C.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    # ---------------------------------------------------------------- building blocks
+    def ttm(self, x, mode: int, U):
+        """x x_mode U^T (U is x.shape[mode] x r)."""
+        import torch
+        x = _f32_device(x, "x")
+        U = _f32_device(U, "U")
+        dims = list(x.shape)
+        out_dims = list(dims)
+        out_dims[mode] = int(U.shape[1])
+        out = torch.empty(out_dims, dtype=torch.float32, device=x.device)
+        _check(_lib.lib().tucker_ttm(self._h, C.c_void_p(x.data_ptr()), len(dims), _lib.i64(dims), int(mode),
+                                     C.c_void_p(U.data_ptr()), int(U.shape[1]), C.c_void_p(out.data_ptr())),
+               self._h)
+        return out
+
+    def gram(self, x, mode: int):
+        import torch
+        x = _f32_device(x, "x")
+        dims = list(x.shape)
+        out = torch.empty((dims[mode], dims[mode]), dtype=torch.float32, device=x.device)
+        _check(_lib.lib().tucker_gram(self._h, C.c_void_p(x.data_ptr()), len(dims), _lib.i64(dims), int(mode),
+                                      C.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def orthonormalize(self, Z):
+        import torch
+        Z = _f32_device(Z, "Z")
+        out = torch.empty_like(Z)
+        _check(_lib.lib().tucker_orthonormalize(self._h, C.c_void_p(Z.data_ptr()), int(Z.shape[0]),
+                                                int(Z.shape[1]), C.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def gram_tn64(self, Z):
+        """Z^T Z accumulated in FP64 (float64 result)."""
+        import torch
+        Z = _f32_device(Z, "Z")
+        W = torch.empty((Z.shape[1], Z.shape[1]), dtype=torch.float64, device=Z.device)
+        _check(_lib.lib().tucker_gram_tn64(self._h, C.c_void_p(Z.data_ptr()), int(Z.shape[0]), int(Z.shape[1]),
+                                           C.c_void_p(W.data_ptr())), self._h)
+        return W
+
+    def chol_inv(self, W):
+        """T = L^-1 D^-1 for D^-1 W D^-1 = L L^T (float64 in and out)."""
+        import torch
+        if W.dtype != torch.float64 or W.device.type != "cuda":
+            raise TypeError("W must be a float64 CUDA tensor")
+        W = W.contiguous()
+        T = torch.empty_like(W)
+        _check(_lib.lib().tucker_chol_inv(self._h, C.c_void_p(W.data_ptr()), int(W.shape[0]),
+                                          C.c_void_p(T.data_ptr())), self._h)
+        return T
+
+    def sym_eig(self, S, r: int):
+        import torch
+        S = _f32_device(S, "S")
+        n = int(S.shape[0])
+        U = torch.empty((n, r), dtype=torch.float32, device=S.device)
+        lam = torch.empty((n,), dtype=torch.float64, device=S.device)
+        _check(_lib.lib().tucker_sym_eig(self._h, C.c_void_p(S.data_ptr()), n, int(r), C.c_void_p(U.data_ptr()),
+                                         C.c_void_p(lam.data_ptr())), self._h)
+        return U, lam
+
+    def sumsq(self, x) -> float:
+        x = _f32_device(x, "x")
+        out = C.c_double(0.0)
+        _check(_lib.lib().tucker_sumsq(self._h, C.c_void_p(x.data_ptr()), int(x.numel()), C.byref(out)), self._h)
+        return float(out.value)
+
+    def stats(self) -> dict:
+        st = _lib.Stats()
+        _check(_lib.lib().tucker_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.Stats._fields_}
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def decompose(x, ranks, max_iters: int = 10, tol: float = 0.0, init_factors=None) -> Result:
+    return default_context(x.device.index or 0).decompose(x, ranks, max_iters, tol, init_factors)
+
+
+def reconstruct(core, factors):
+    return default_context(core.device.index or 0).reconstruct(core, factors)

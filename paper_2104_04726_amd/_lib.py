@@ -1,0 +1,112 @@
+"""ctypes declarations for libtucker_mi355x.so (the C ABI of include/tucker.h).
+
+The library is loaded from this package directory; there is no fallback implementation:
+a missing or unloadable library raises at first use.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtucker_mi355x.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tucker.h")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERICAL, ERR_UNSUPPORTED = range(6)
+FP32, BF16, FP16, FP8_E4M3 = range(4)
+MAX_ORDER = 8
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("device", C.c_int),
+        ("stream", C.c_void_p),
+        ("precision", C.c_int),
+        ("refine_sweeps", C.c_int),
+        ("inner_iters", C.c_int),
+        ("init_iters", C.c_int),
+        ("inner_tol", C.c_double),
+        ("use_graphs", C.c_int),
+        ("hbm_budget_bytes", C.c_size_t),
+        ("seed", C.c_uint64),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("init_ms", C.c_double),
+        ("sweeps_ms", C.c_double),
+        ("final_fit_ms", C.c_double),
+        ("fit_gram", C.c_double),
+        ("sweeps", C.c_int),
+        ("chol_shifts", C.c_int),
+        ("workspace_bytes", C.c_size_t),
+    ]
+
+
+_lib = None
+
+I64P = C.POINTER(C.c_int64)
+FPP = C.POINTER(C.c_void_p)
+
+
+def _declare(lib):
+    v = C.c_void_p
+    lib.tucker_default_options.argtypes = [C.POINTER(Options)]
+    lib.tucker_default_options.restype = None
+    lib.tucker_validate.argtypes = [C.c_int, I64P, I64P, C.c_int, C.c_double]
+    lib.tucker_workspace_size.argtypes = [C.c_int, I64P, I64P, C.c_int, C.POINTER(C.c_size_t)]
+    lib.tucker_create.argtypes = [C.POINTER(Options), C.POINTER(v)]
+    lib.tucker_destroy.argtypes = [v]
+    lib.tucker_decompose.argtypes = [v, v, C.c_int, I64P, I64P, C.c_int, C.c_double, v, FPP,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.tucker_decompose_ex.argtypes = [v, v, C.c_int, I64P, I64P, C.c_int, C.c_double, FPP, v, FPP,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.tucker_reconstruct.argtypes = [v, v, FPP, C.c_int, I64P, I64P, v]
+    lib.tucker_ttm.argtypes = [v, v, C.c_int, I64P, C.c_int, v, C.c_int64, v]
+    lib.tucker_gram.argtypes = [v, v, C.c_int, I64P, C.c_int, v]
+    lib.tucker_orthonormalize.argtypes = [v, v, C.c_int64, C.c_int64, v]
+    lib.tucker_gram_tn64.argtypes = [v, v, C.c_int64, C.c_int64, v]
+    lib.tucker_chol_inv.argtypes = [v, v, C.c_int64, v]
+    lib.tucker_sym_eig.argtypes = [v, v, C.c_int64, C.c_int64, v, v]
+    lib.tucker_sumsq.argtypes = [v, v, C.c_int64, C.POINTER(C.c_double)]
+    lib.tucker_status_string.argtypes = [C.c_int]
+    lib.tucker_status_string.restype = C.c_char_p
+    lib.tucker_last_error.argtypes = [v]
+    lib.tucker_last_error.restype = C.c_char_p
+    lib.tucker_get_stats.argtypes = [v, C.POINTER(Stats)]
+    for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
+                 "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
+                 "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv", "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):
+        getattr(lib, name).restype = C.c_int
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_2104_04726_amd.build`)")
+        handle = C.CDLL(LIB_PATH)
+        _declare(handle)
+        _lib = handle
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/tucker.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tucker_[a-z0-9_]+)\s*\(", text)))
+
+
+def i64(vals):
+    arr = (C.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def status_name(code: int) -> str:
+    return lib().tucker_status_string(int(code)).decode()

@@ -1,0 +1,1143 @@
+// Host driver and C ABI of the Tucker-ALS (HOOI) library.
+//
+// Algorithm (Sharma & Grover, arXiv 2104.04726, Sec. III-B):
+//   * T-HOSVD start (Sec. III-B.1, eq. (3)-(7)): U_n = leading R_n eigenvectors of X_(n) X_(n)^T.
+//   * ALS sweeps (eq. (8)): for n = 1..N in order, Y = X x_{m != n} U_m^T with the newest factors,
+//     U_n <- leading R_n eigenvectors of Y_(n) Y_(n)^T (the Gram route the paper takes to avoid
+//     a large SVD); the core G = Y x_N U_N^T closes the sweep.
+// Realisation on one GPU:
+//   * modes with R_n = s_n keep their (orthonormal) factor: any basis of R^{s_n} is optimal;
+//   * modes with s_n <= 64: the Gram is diagonalised exactly by Jacobi in FP64;
+//   * larger modes: orthogonal iteration warm-started from the previous U_n: Z = S U (FP32 MFMA),
+//     U <- CholeskyQR2(Z) in FP64 (cold start from a counter-based random basis for the T-HOSVD);
+//   * order-4 tensors whose two trailing modes are small (the image stacks: H, W, channel, image)
+//     use a dimension tree: T34 = X x_3 U_3^T x_4 U_4^T serves modes 1 and 2, T12 = X x_1 U_1^T x_2 U_2^T
+//     serves modes 3, 4 and the core; other shapes contract each chain directly;
+//   * fit: ||X||^2 - ||G||^2 per sweep (FP64 sums), and at the end 1 - ||X - Xhat|| / ||X|| from the
+//     explicit residual, fused into the last expanding product.
+#include <algorithm>
+#include <functional>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tk_common.h"
+#include "../../include/tucker.h"
+
+using namespace tk;
+
+hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s);
+hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
+                          hipStream_t s);
+
+struct tucker_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tucker_options opt{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    tucker_stats stats{};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int64_t kSmallMode = 64;       // modes up to this size are diagonalised exactly
+
+struct Fail {
+    tucker_status st;
+    std::string msg;
+};
+
+#define TK_HIP(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            throw Fail{TUCKER_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+int64_t prod(const int64_t* d, int a, int b) {
+    int64_t p = 1;
+    for (int i = a; i < b; ++i) p *= d[i];
+    return p;
+}
+
+// ------------------------------------------------------------------ bump arena over one block
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    size_t cap = 0;     // 0 while sizing
+    template <typename T>
+    T* take(int64_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        if (base && off > cap) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "workspace plan overflow"};
+        return p;
+    }
+};
+
+enum ModeKind { FIXED = 0, SMALL = 1, LARGE = 2 };
+
+// ------------------------------------------------------------------ plan and buffers
+struct Plan {
+    int N = 0;
+    int64_t s[TUCKER_MAX_ORDER]{}, R[TUCKER_MAX_ORDER]{};
+    ModeKind kind[TUCKER_MAX_ORDER]{};
+    bool tree = false;
+    int max_iters = 0;
+
+    float* U32[TUCKER_MAX_ORDER]{};
+    double* U64[TUCKER_MAX_ORDER]{};
+    // tree buffers
+    float *T34 = nullptr, *Y0 = nullptr, *Y1 = nullptr, *T1 = nullptr, *T12 = nullptr;
+    // generic chain buffers
+    float *Ya = nullptr, *Yb = nullptr;
+    float* G = nullptr;
+    // Gram / OI
+    float* S32 = nullptr;
+    double* S64 = nullptr;
+    float* P = nullptr;
+    int64_t P_elems = 0;
+    float* Z = nullptr;
+    double* Q1 = nullptr;
+    double* W = nullptr;
+    double* Wpart = nullptr;
+    int64_t Wpart_elems = 0;
+    double* Tm = nullptr;
+    void* chol_ws = nullptr;
+    double* F = nullptr;
+    double* Fpart = nullptr;
+    // norms and fits
+    double* red = nullptr;       // kSumsqBlocks partials
+    double* rpart = nullptr;     // residual partials (one per GEMM block)
+    int64_t rpart_elems = 0;
+    double* scal = nullptr;      // [0] nx2 [1] ng2 [2] r2 [3] fit_exact
+    double* fits = nullptr;      // max_iters + 1
+    int* shifts = nullptr;
+    float* Xh = nullptr;         // explicit reconstruction when the residual cannot be fused
+};
+
+int64_t max_large_s(const Plan& p) {
+    int64_t m = 0;
+    for (int n = 0; n < p.N; ++n)
+        if (p.kind[n] == LARGE) m = std::max(m, p.s[n]);
+    return m;
+}
+int64_t max_large_sR(const Plan& p) {
+    int64_t m = 0;
+    for (int n = 0; n < p.N; ++n)
+        if (p.kind[n] == LARGE) m = std::max(m, p.s[n] * p.R[n]);
+    return m;
+}
+int64_t max_large_R(const Plan& p) {
+    int64_t m = 0;
+    for (int n = 0; n < p.N; ++n)
+        if (p.kind[n] == LARGE) m = std::max(m, p.R[n]);
+    return m;
+}
+
+// largest intermediate of the direct chains (generic path), including reconstruction chains
+int64_t chain_max(const Plan& p) {
+    int64_t mx = 0;
+    for (int n = 0; n < p.N; ++n) {
+        int64_t d[TUCKER_MAX_ORDER];
+        for (int i = 0; i < p.N; ++i) d[i] = p.s[i];
+        for (int m = 0; m < p.N; ++m) {
+            if (m == n) continue;
+            d[m] = p.R[m];
+            mx = std::max(mx, prod(d, 0, p.N));
+        }
+    }
+    // core chain and reconstruction chain (from the core up)
+    int64_t d[TUCKER_MAX_ORDER];
+    for (int i = 0; i < p.N; ++i) d[i] = p.R[i];
+    for (int m = p.N - 1; m >= 0; --m) {
+        d[m] = p.s[m];
+        mx = std::max(mx, prod(d, 0, p.N));
+    }
+    return mx;
+}
+
+constexpr int kGramTargetBlocks = 1024;
+
+int gram_splits(int64_t s, int64_t K) {
+    const int64_t t = (s + 127) / 128;
+    const int64_t tiles = t * (t + 1) / 2;
+    int64_t sp = (kGramTargetBlocks + tiles - 1) / tiles;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
+    sp = std::max<int64_t>(sp, 1);
+    return (int)std::min<int64_t>(sp, 64);
+}
+
+void build_plan(Plan& p, Arena& a) {
+    const int N = p.N;
+    for (int n = 0; n < N; ++n) {
+        p.U32[n] = a.take<float>(p.s[n] * p.R[n]);
+        p.U64[n] = a.take<double>(p.s[n] * p.R[n]);
+    }
+    const int64_t Xn = prod(p.s, 0, N);
+    if (p.tree) {
+        const int64_t s0 = p.s[0], s1 = p.s[1], L = p.s[2] * p.s[3], R23 = p.R[2] * p.R[3];
+        p.T34 = a.take<float>(s0 * s1 * R23);
+        p.Y0 = a.take<float>(s0 * p.R[1] * R23);
+        p.Y1 = a.take<float>(p.R[0] * s1 * R23);
+        p.T1 = a.take<float>(p.R[0] * s1 * L);
+        p.T12 = a.take<float>(p.R[0] * p.R[1] * L);
+        p.F = a.take<double>(64 * 64);
+        p.Fpart = a.take<double>(std::max<int64_t>((int64_t)kFibreGramBlocks * L * L, 64 * 64 * 64));
+    } else {
+        const int64_t cm = chain_max(p);
+        p.Ya = a.take<float>(cm);
+        p.Yb = a.take<float>(cm);
+    }
+    p.G = a.take<float>(prod(p.R, 0, N));
+    // Grams: largest split-K partial buffer over the large modes, init (X) and sweep shapes
+    int64_t maxs = 0, pmax = 0, maxsmall = 1;
+    for (int n = 0; n < N; ++n) {
+        if (p.kind[n] == LARGE) {
+            const int64_t sn = p.s[n];
+            maxs = std::max(maxs, sn);
+            const int64_t Kx = Xn / sn;
+            int64_t Ky = prod(p.R, 0, N) / p.R[n];   // sweep Gram inner size
+            const int64_t K = std::max(Kx, Ky);
+            pmax = std::max(pmax, (int64_t)gram_splits(sn, K) * sn * sn);
+        } else {
+            maxsmall = std::max(maxsmall, p.s[n]);
+        }
+    }
+    p.S32 = a.take<float>(std::max<int64_t>(maxs * maxs, 1));
+    p.S64 = a.take<double>(std::max<int64_t>(std::max(maxs, maxsmall) * std::max(maxs, maxsmall), 64 * 64));
+    p.P = a.take<float>(pmax);
+    p.P_elems = pmax;
+    const int64_t sR = max_large_sR(p), Rm = max_large_R(p);
+    p.Z = a.take<float>(sR);
+    p.Q1 = a.take<double>(sR);
+    p.W = a.take<double>(Rm * Rm);
+    p.Wpart_elems = 16 * Rm * Rm;
+    p.Wpart = a.take<double>(p.Wpart_elems);
+    p.Tm = a.take<double>(Rm * Rm);
+    p.chol_ws = a.take<char>(chol_counter_ints(Rm) * 4 + 64 + Rm * 8);
+    if (!p.tree) {
+        p.F = a.take<double>(64 * 64);
+        p.Fpart = a.take<double>(64 * 64 * 64);
+    }
+    p.red = a.take<double>(kSumsqBlocks);
+    p.rpart_elems = std::max<int64_t>(4096, (Xn / (128 * 128)) + 4096);
+    p.rpart = a.take<double>(p.rpart_elems);
+    p.scal = a.take<double>(8);
+    p.fits = a.take<double>(p.max_iters + 2);
+    p.shifts = a.take<int>(4);
+    if (!p.tree) p.Xh = (p.kind[0] == LARGE && p.s[0] > kSmallMode) ? nullptr : a.take<float>(Xn);
+}
+
+// ------------------------------------------------------------------ driver state
+struct Run {
+    tucker_ctx* ctx;
+    Plan p;
+    hipStream_t st;
+    const float* X = nullptr;
+};
+
+// out = in x_n U^T (contract, U: dims[n] x R)  or  in x_n U (expand, U: s x dims[n], result dim s)
+// dims: current dims of `in` (order N); the new size of mode n is newdim.
+// When resid_ref is set (only for an expanding GEMM), the product is not stored: the squared
+// difference against resid_ref (same layout as the product) is summed into rpart.
+void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float* U, int64_t newdim,
+         bool expand, float* out, const float* resid_ref = nullptr, int64_t* nblocks = nullptr) {
+    const int64_t A = prod(dims, 0, n), K = dims[n], B = prod(dims, n + 1, N);
+    const int64_t R = newdim;
+    if (!resid_ref && K <= kSmallMode && R <= kSmallMode) {
+        TK_HIP(small_ttm(in, A, K, B, U, R, expand, out, r.st));
+        return;
+    }
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.k_split = 0;
+    g.c_zstride = 0;
+    g.lower_only = 0;
+    Orient oa, ob;
+    if (B == 1) {
+        // C(m = a, n = r) = sum_k in[a][k] * Uop(k, r)
+        g.M = A;
+        g.N = R;
+        g.K = K;
+        g.a = plain(in, K);
+        oa = MK;
+        if (!expand) {
+            g.b = plain(U, R);   // U[k][r]
+            ob = KM;
+        } else {
+            g.b = plain(U, K);   // U[r][k]: (k, n=r) at r*K + k
+            ob = MK;
+        }
+        g.c = plain(resid_ref ? (const void*)resid_ref : (const void*)out, R);
+    } else {
+        g.M = R;
+        g.N = A * B;
+        g.K = K;
+        if (!expand) {
+            g.a = plain(U, R);   // A(m=r, k) = U[k][r]
+            oa = KM;
+        } else {
+            g.a = plain(U, K);   // A(m=i, k=r) = U[i][r]
+            oa = MK;
+        }
+        g.b = folded(in, B, B, K * B);
+        ob = KM;
+        g.c = folded(resid_ref ? (const void*)resid_ref : (const void*)out, B, B, R * B);
+    }
+    if (resid_ref) {
+        const int64_t nb = gemm_grid_blocks(g, false);
+        if (nb > r.p.rpart_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "residual partial buffer too small"};
+        g.resid_partial = r.p.rpart;
+        TK_HIP(gemm_f32(g, oa, ob, EPI_RESID, false, r.st));
+        if (nblocks) *nblocks = nb;
+    } else {
+        TK_HIP(gemm_f32(g, oa, ob, EPI_STORE, false, r.st));
+    }
+}
+
+// Mode-n Gram of `in` (dims, order N).  LARGE: FP32 result in S32 (and FP64 in S64 when asked).
+// Small (s <= 64): FP64 result in S64.
+void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want64) {
+    Plan& p = r.p;
+    const int64_t A = prod(dims, 0, n), s = dims[n], B = prod(dims, n + 1, N);
+    if (s <= kSmallMode) {
+        TK_HIP(small_gram(in, A, s, B, p.Fpart, kFibreGramBlocks / 8, p.S64, r.st));
+        return;
+    }
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.lower_only = 1;
+    g.M = s;
+    g.N = s;
+    Orient oa, ob;
+    if (B == 1) {
+        g.K = A;
+        g.a = plain(in, s);   // (m=i, k=a) at a*s + i
+        g.b = plain(in, s);
+        oa = KM;
+        ob = KM;
+    } else {
+        g.K = A * B;
+        g.a = folded(in, B, B, s * B);   // (m=i, k=(a,b)) at i*B + a*s*B + b
+        g.b = g.a;
+        oa = MK;
+        ob = MK;
+    }
+    const int splits = gram_splits(s, g.K);
+    int64_t ks = (g.K + splits - 1) / splits;
+    ks = (ks + 31) / 32 * 32;
+    g.k_split = ks;
+    const int nsplit = (int)((g.K + ks - 1) / ks);
+    if ((int64_t)nsplit * s * s > p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer too small"};
+    g.c = plain(p.P, s);
+    g.c_zstride = s * s;
+    TK_HIP(gemm_f32(g, oa, ob, EPI_STORE, true, r.st));
+    TK_HIP(gram_reduce(p.P, nsplit, s, s * s, p.S32, want64 ? p.S64 : nullptr, r.st));
+}
+
+// W = A^T A (FP64) for A (rows x cols), A float or double, split over rows
+void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, double* W) {
+    Plan& p = r.p;
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = cols;
+    g.N = cols;
+    g.K = rows;
+    g.a = plain(A, cols);
+    g.b = plain(A, cols);
+    const int64_t tiles = ((cols + 63) / 64) * ((cols + 63) / 64);
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(16, (512 + tiles - 1) / tiles));
+    splits = std::min<int64_t>(splits, std::max<int64_t>(1, rows / 64));
+    int64_t ks = (rows + splits - 1) / splits;
+    ks = (ks + 15) / 16 * 16;
+    const int nsplit = (int)((rows + ks - 1) / ks);
+    g.k_split = ks;
+    if ((int64_t)nsplit * cols * cols > p.Wpart_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "W partial buffer"};
+    if (nsplit == 1) {
+        g.c = plain(W, cols);
+        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, a32, a32, r.st));
+        return;
+    }
+    g.c = plain(p.Wpart, cols);
+    g.c_zstride = cols * cols;
+    TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, a32, a32, r.st));
+    TK_HIP(tk_sum_splits_f64(p.Wpart, nsplit, cols * cols, cols * cols, W, r.st));
+}
+
+// Q = A T^T (A rows x cols float/double, T cols x cols lower-triangular fp64) -> Q fp64
+void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, const double* Tm, double* Q) {
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = rows;
+    g.N = cols;
+    g.K = cols;
+    g.a = plain(A, cols);      // (m=row, k) at row*cols + k
+    g.b = plain(Tm, cols);     // (k, n) = T[n][k] -> NK
+    g.c = plain(Q, cols);
+    g.k_split = 0;
+    TK_HIP(gemm_f64(g, MK, MK, EPI_STORE, a32, false, r.st));
+}
+
+// U64/U32 <- orthonormal basis of span(Z) by two column-scaled CholeskyQR passes (FP64)
+void orthonormalize(Run& r, const float* Z, int64_t rows, int64_t cols, double* U64, float* U32) {
+    Plan& p = r.p;
+    gram_tn64(r, Z, true, rows, cols, p.W);
+    TK_HIP(chol_inv_scaled(p.W, cols, true, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    apply_tri(r, Z, true, rows, cols, p.Tm, p.Q1);
+    gram_tn64(r, p.Q1, false, rows, cols, p.W);
+    TK_HIP(chol_inv_scaled(p.W, cols, true, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
+    TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
+}
+
+// q steps of orthogonal iteration on S32 (s x s), warm start from U32
+void orth_iter(Run& r, int n, int q) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n], R = p.R[n];
+    for (int it = 0; it < q; ++it) {
+        GemmArgs g{};
+        g.alpha = 1.0;
+        g.M = s;
+        g.N = R;
+        g.K = s;
+        g.a = plain(p.S32, s);      // A(m, k) = S[k][m] (symmetric)
+        g.b = plain(p.U32[n], R);
+        g.c = plain(p.Z, R);
+        TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
+        orthonormalize(r, p.Z, s, R, p.U64[n], p.U32[n]);
+    }
+}
+
+// factor update of mode n from the Gram already in S32 / S64
+void update_factor(Run& r, int n, bool cold) {
+    Plan& p = r.p;
+    if (p.kind[n] == FIXED) return;
+    if (p.kind[n] == SMALL) {
+        TK_HIP(jacobi_eig(p.S64, (int)p.s[n], (int)p.R[n], p.U64[n], p.U32[n], nullptr, r.st));
+        return;
+    }
+    if (cold) {
+        TK_HIP(fill_random(p.U32[n], p.s[n] * p.R[n], r.ctx->opt.seed * 0x100000001b3ull + (uint64_t)n * 0x9e3779b9ull,
+                           r.st));
+        orth_iter(r, n, std::max(1, r.ctx->opt.init_iters));
+    } else {
+        orth_iter(r, n, std::max(1, r.ctx->opt.inner_iters));
+    }
+}
+
+void identity_factor(Run& r, int n) {
+    TK_HIP(fill_identity_f32(r.p.U32[n], r.p.s[n], r.p.R[n], r.st));
+    TK_HIP(fill_identity_f64(r.p.U64[n], r.p.s[n], r.p.R[n], r.st));
+}
+
+// G = X x_1 U1^T ... x_N UN^T into p.G
+void core_from_x(Run& r) {
+    Plan& p = r.p;
+    const int N = p.N;
+    if (p.tree) {
+        int64_t d[4] = {p.s[0], p.s[1], p.s[2] * p.s[3], 1};
+        ttm(r, r.X, d, 3, 0, p.U32[0], p.R[0], false, p.T1);
+        d[0] = p.R[0];
+        ttm(r, p.T1, d, 3, 1, p.U32[1], p.R[1], false, p.T12);
+        TK_HIP(pair_ttm(p.T12, p.R[0] * p.R[1], (int)p.s[2], (int)p.s[3], p.U32[2], (int)p.R[2], p.U32[3], (int)p.R[3],
+                        false, p.G, r.st));
+        return;
+    }
+    int64_t d[TUCKER_MAX_ORDER];
+    for (int i = 0; i < N; ++i) d[i] = p.s[i];
+    const float* cur = r.X;
+    float* bufs[2] = {p.Ya, p.Yb};
+    int w = 0;
+    for (int m = 0; m < N; ++m) {
+        float* dst = (m == N - 1) ? p.G : bufs[w];
+        ttm(r, cur, d, N, m, p.U32[m], p.R[m], false, dst);
+        d[m] = p.R[m];
+        cur = dst;
+        w ^= 1;
+    }
+}
+
+void core_norm_and_fit(Run& r, double* fit_slot) {
+    Plan& p = r.p;
+    TK_HIP(sumsq_f32(p.G, prod(p.R, 0, p.N), p.red, kSumsqBlocks, p.scal + 1, r.st));
+    TK_HIP(fit_from_norms(p.scal + 0, p.scal + 1, fit_slot, r.st));
+}
+
+// ------------------------------------------------------------------ T-HOSVD initialisation
+void thosvd(Run& r) {
+    Plan& p = r.p;
+    for (int n = 0; n < p.N; ++n) {
+        if (p.kind[n] == FIXED) {
+            identity_factor(r, n);
+            continue;
+        }
+        gram(r, r.X, p.s, p.N, n, false);
+        update_factor(r, n, true);
+    }
+}
+
+// ------------------------------------------------------------------ one ALS sweep
+void sweep_tree(Run& r) {
+    Plan& p = r.p;
+    const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3];
+    const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3];
+    const int64_t R23 = R2 * R3, L = s2 * s3;
+    // T34 = X x_3 U3^T x_4 U4^T (full-tensor pass, memory-bound)
+    TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.T34, r.st));
+    // mode 1: Y0 = T34 x_2 U2^T, S0 = Y0_(1) Y0_(1)^T
+    if (p.kind[0] != FIXED) {
+        int64_t d[3] = {s0, s1, R23};
+        ttm(r, p.T34, d, 3, 1, p.U32[1], R1, false, p.Y0);
+        int64_t dy[3] = {s0, R1, R23};
+        gram(r, p.Y0, dy, 3, 0, p.kind[0] == SMALL);
+        update_factor(r, 0, false);
+    }
+    // mode 2: Y1 = T34 x_1 U1^T (new U1), S1
+    if (p.kind[1] != FIXED) {
+        int64_t d[3] = {s0, s1, R23};
+        ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
+        int64_t dy[3] = {R0, s1, R23};
+        gram(r, p.Y1, dy, 3, 1, p.kind[1] == SMALL);
+        update_factor(r, 1, false);
+    }
+    // T12 = X x_1 U1^T x_2 U2^T (second full-tensor pass)
+    {
+        int64_t d[3] = {s0, s1, L};
+        ttm(r, r.X, d, 3, 0, p.U32[0], R0, false, p.T1);
+        d[0] = R0;
+        ttm(r, p.T1, d, 3, 1, p.U32[1], R1, false, p.T12);
+    }
+    // modes 3 and 4 from the fibre Gram of T12
+    if (p.kind[2] != FIXED || p.kind[3] != FIXED) {
+        TK_HIP(fibre_gram(p.T12, R0 * R1, (int)L, p.Fpart, kFibreGramBlocks, p.F, r.st));
+        if (p.kind[2] != FIXED) {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[3], (int)R3, 3, p.S64, r.st));
+            update_factor(r, 2, false);
+        }
+        if (p.kind[3] != FIXED) {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[2], (int)R2, 4, p.S64, r.st));
+            update_factor(r, 3, false);
+        }
+    }
+    // core G = T12 x_3 U3^T x_4 U4^T
+    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
+}
+
+void sweep_generic(Run& r) {
+    Plan& p = r.p;
+    const int N = p.N;
+    float* bufs[2] = {p.Ya, p.Yb};
+    int64_t d[TUCKER_MAX_ORDER];
+    const float* cur = nullptr;
+    for (int n = 0; n < N; ++n) {
+        for (int i = 0; i < N; ++i) d[i] = p.s[i];
+        cur = r.X;
+        int w = 0;
+        for (int m = 0; m < N; ++m) {
+            if (m == n) continue;
+            ttm(r, cur, d, N, m, p.U32[m], p.R[m], false, bufs[w]);
+            d[m] = p.R[m];
+            cur = bufs[w];
+            w ^= 1;
+        }
+        if (p.kind[n] != FIXED) {
+            gram(r, cur, d, N, n, p.kind[n] == SMALL);
+            update_factor(r, n, false);
+        }
+    }
+    // core from the last chain: G = Y x_N U_N^T
+    ttm(r, cur, d, N, N - 1, p.U32[N - 1], p.R[N - 1], false, p.G);
+}
+
+// ------------------------------------------------------------------ reconstruction chain
+// Expands G through all factors.  With out == nullptr the last product is fused with the
+// residual against X and ||X - Xhat||^2 lands in scal[2].
+void expand_chain(Run& r, const float* G, float* const* U, float* out, const float* Xref) {
+    Plan& p = r.p;
+    const int N = p.N;
+    if (p.tree) {
+        const int64_t R0 = p.R[0], R1 = p.R[1], s2 = p.s[2], s3 = p.s[3];
+        TK_HIP(pair_ttm(G, R0 * R1, (int)s2, (int)s3, U[2], (int)p.R[2], U[3], (int)p.R[3], true, p.T12, r.st));
+        int64_t d[3] = {R0, R1, s2 * s3};
+        ttm(r, p.T12, d, 3, 1, U[1], p.s[1], true, p.T1);
+        d[1] = p.s[1];
+        if (Xref) {
+            int64_t nb = 0;
+            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, nullptr, Xref, &nb);
+            TK_HIP(reduce_f64(p.rpart, nb, p.scal + 2, r.st));
+        } else {
+            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, out);
+        }
+        return;
+    }
+    int64_t d[TUCKER_MAX_ORDER];
+    for (int i = 0; i < N; ++i) d[i] = p.R[i];
+    float* bufs[2] = {p.Ya, p.Yb};
+    const float* cur = G;
+    int w = 0;
+    const bool fuse = Xref && p.Xh == nullptr;
+    for (int m = N - 1; m >= 0; --m) {
+        if (m == 0 && fuse) {
+            int64_t nb = 0;
+            ttm(r, cur, d, N, 0, U[0], p.s[0], true, nullptr, Xref, &nb);
+            TK_HIP(reduce_f64(p.rpart, nb, p.scal + 2, r.st));
+            return;
+        }
+        float* dst = (m == 0) ? (Xref ? p.Xh : out) : bufs[w];
+        ttm(r, cur, d, N, m, U[m], p.s[m], true, dst);
+        d[m] = p.s[m];
+        cur = dst;
+        w ^= 1;
+    }
+    if (Xref) {
+        TK_HIP(tk_resid_sumsq(Xref, p.Xh, prod(p.s, 0, N), p.red, kSumsqBlocks, p.scal + 2, r.st));
+    }
+}
+
+// ------------------------------------------------------------------ validation
+tucker_status validate_args(int ndim, const int64_t* dims, const int64_t* ranks, int max_iters, double tol,
+                            std::string& why) {
+    if (!dims || !ranks) {
+        why = "dims/ranks is NULL";
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    if (ndim < 2 || ndim > TUCKER_MAX_ORDER) {
+        why = "ndim must be in [2, 8]";
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    long double total_r = 1;
+    int64_t total = 1;
+    for (int n = 0; n < ndim; ++n) {
+        if (dims[n] < 1) {
+            why = "dims must be >= 1";
+            return TUCKER_ERR_INVALID_ARG;
+        }
+        if (ranks[n] < 1 || ranks[n] > dims[n]) {
+            why = "ranks must be in [1, dims]";
+            return TUCKER_ERR_INVALID_ARG;
+        }
+        if (total > (int64_t(1) << 40) / dims[n]) {
+            why = "tensor too large";
+            return TUCKER_ERR_INVALID_ARG;
+        }
+        total *= dims[n];
+        total_r *= (long double)ranks[n];
+    }
+    for (int n = 0; n < ndim; ++n) {
+        if ((long double)ranks[n] * ranks[n] > total_r) {
+            why = "ranks[n] exceeds the product of the other ranks";
+            return TUCKER_ERR_INVALID_ARG;
+        }
+    }
+    if (max_iters < 0) {
+        why = "max_iters must be >= 0";
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    if (!(tol >= 0.0)) {
+        why = "tol must be >= 0 and not NaN";
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    return TUCKER_OK;
+}
+
+void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int max_iters) {
+    p.N = ndim;
+    p.max_iters = max_iters;
+    for (int n = 0; n < ndim; ++n) {
+        p.s[n] = dims[n];
+        p.R[n] = ranks[n];
+        p.kind[n] = (ranks[n] == dims[n]) ? FIXED : (dims[n] <= kSmallMode ? SMALL : LARGE);
+    }
+    p.tree = (ndim == 4) && pair_ttm_supported((int)dims[2], (int)dims[3]) && dims[2] * dims[3] <= 64;
+}
+
+size_t plan_bytes(Plan& p) {
+    Arena a;
+    build_plan(p, a);
+    return a.off + 256;
+}
+
+void ensure_ws(tucker_ctx* ctx, size_t bytes) {
+    if (ctx->opt.hbm_budget_bytes && bytes > ctx->opt.hbm_budget_bytes)
+        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "workspace exceeds hbm_budget_bytes"};
+    if (bytes <= ctx->ws_bytes) return;
+    if (ctx->ws) {
+        TK_HIP(hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->ws, bytes);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, std::string("hipMalloc workspace: ") + hipGetErrorString(e)};
+    }
+    ctx->ws_bytes = bytes;
+    ctx->stats.workspace_bytes = bytes;
+}
+
+void bind(tucker_ctx* ctx, Plan& p) {
+    const size_t need = plan_bytes(p);
+    ensure_ws(ctx, need);
+    Arena a;
+    a.base = (char*)ctx->ws;
+    a.cap = ctx->ws_bytes;
+    build_plan(p, a);
+}
+
+}  // namespace
+
+// helpers defined in this TU but called through extern declarations above
+namespace {
+__global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int64_t n, int64_t zstride,
+                                  double* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int z = 0; z < nsplit; ++z) s += P[z * zstride + e];
+        out[e] = s;
+    }
+}
+__global__ void resid_kernel(const float* __restrict__ X, const float* __restrict__ Xh, int64_t n,
+                             double* __restrict__ partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)X[i] - (double)Xh[i];
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+}  // namespace
+
+hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+    hipLaunchKernelGGL(sum_splits_kernel, dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
+    return hipGetLastError();
+}
+hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(resid_kernel, dim3(nblocks), dim3(256), 0, s, X, Xh, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_f64(partial, nblocks, out, s);
+}
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+namespace {
+
+template <typename Fn>
+tucker_status guarded(tucker_ctx* ctx, Fn fn) {
+    try {
+        TK_HIP(hipSetDevice(ctx->device));
+        fn();
+        return TUCKER_OK;
+    } catch (const Fail& f) {
+        ctx->err = f.msg;
+        (void)hipGetLastError();
+        return f.st;
+    } catch (const std::exception& e) {
+        ctx->err = e.what();
+        return TUCKER_ERR_DEVICE;
+    }
+}
+
+double elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+    }
+    return (double)ms;
+}
+
+// scratch arena for the step-level entry points
+template <typename Fn>
+void with_scratch(tucker_ctx* ctx, Fn layout) {
+    Arena a;
+    layout(a);
+    ensure_ws(ctx, a.off + 256);
+    Arena b;
+    b.base = (char*)ctx->ws;
+    b.cap = ctx->ws_bytes;
+    layout(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tucker_default_options(tucker_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->precision = TUCKER_FP32;
+    o->refine_sweeps = 1;
+    o->inner_iters = 1;
+    o->init_iters = 20;
+    o->inner_tol = 0.0;
+    o->use_graphs = 0;
+    o->hbm_budget_bytes = 0;
+    o->seed = 0x5eedull;
+}
+
+tucker_status tucker_validate(int ndim, const int64_t* dims, const int64_t* ranks, int max_iters, double tol) {
+    std::string why;
+    return validate_args(ndim, dims, ranks, max_iters, tol, why);
+}
+
+tucker_status tucker_workspace_size(int ndim, const int64_t* dims, const int64_t* ranks, tucker_precision precision,
+                                    size_t* bytes) {
+    std::string why;
+    tucker_status st = validate_args(ndim, dims, ranks, 0, 0.0, why);
+    if (st != TUCKER_OK) return st;
+    if (!bytes || precision < TUCKER_FP32 || precision > TUCKER_FP8_E4M3) return TUCKER_ERR_INVALID_ARG;
+    Plan p;
+    make_plan(p, ndim, dims, ranks, 0);
+    *bytes = plan_bytes(p);
+    return TUCKER_OK;
+}
+
+tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
+    if (!out) return TUCKER_ERR_INVALID_ARG;
+    *out = nullptr;
+    tucker_options o;
+    tucker_default_options(&o);
+    if (opts) o = *opts;
+    if (o.inner_iters < 1 || o.init_iters < 1 || o.refine_sweeps < 0 || o.precision < TUCKER_FP32 ||
+        o.precision > TUCKER_FP8_E4M3 || o.device < 0)
+        return TUCKER_ERR_INVALID_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return TUCKER_ERR_DEVICE;
+    }
+    if (o.device >= count) return TUCKER_ERR_DEVICE;
+    if (hipSetDevice(o.device) != hipSuccess) {
+        (void)hipGetLastError();
+        return TUCKER_ERR_DEVICE;
+    }
+    tucker_ctx* c = new tucker_ctx();
+    c->device = o.device;
+    c->opt = o;
+    // NULL selects the device's default (null) stream, which orders with other default-stream
+    // work such as a framework's copies.
+    c->stream = (hipStream_t)o.stream;
+    c->own_stream = false;
+    for (auto& e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            tucker_destroy(c);
+            return TUCKER_ERR_DEVICE;
+        }
+    }
+    *out = c;
+    return TUCKER_OK;
+}
+
+tucker_status tucker_destroy(tucker_ctx* ctx) {
+    if (!ctx) return TUCKER_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return TUCKER_OK;
+}
+
+tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim, const int64_t* dims,
+                                  const int64_t* ranks, int max_iters, double tol,
+                                  const float* const* init_factors, float* core, float* const* factors,
+                                  double* fit, double* fit_history, int* sweeps_done) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    ctx->err.clear();
+    std::string why;
+    tucker_status st = validate_args(ndim, dims, ranks, max_iters, tol, why);
+    if (st != TUCKER_OK) {
+        ctx->err = why;
+        return st;
+    }
+    if (!tensor || !core || !factors || !fit) {
+        ctx->err = "NULL tensor/core/factors/fit";
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    for (int n = 0; n < ndim; ++n) {
+        if (!factors[n] || (init_factors && !init_factors[n])) {
+            ctx->err = "NULL factor pointer";
+            return TUCKER_ERR_INVALID_ARG;
+        }
+    }
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, tensor};
+        Plan& p = r.p;
+        make_plan(p, ndim, dims, ranks, max_iters);
+        bind(ctx, p);
+        const hipStream_t s = r.st;
+        TK_HIP(fill_zero(p.shifts, 16, s));
+        TK_HIP(hipEventRecord(ctx->ev[0], s));
+        const int64_t Xn = prod(p.s, 0, p.N);
+        TK_HIP(sumsq_f32(tensor, Xn, p.red, kSumsqBlocks, p.scal + 0, s));
+        double nx2 = 0.0;
+        TK_HIP(hipMemcpyAsync(&nx2, p.scal + 0, sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        if (!std::isfinite(nx2)) throw Fail{TUCKER_ERR_NUMERICAL, "||X||^2 is not finite"};
+        if (nx2 == 0.0) {
+            TK_HIP(fill_zero(core, prod(p.R, 0, p.N) * (int64_t)sizeof(float), s));
+            for (int n = 0; n < p.N; ++n) TK_HIP(fill_identity_f32(factors[n], p.s[n], p.R[n], s));
+            TK_HIP(hipStreamSynchronize(s));
+            *fit = 1.0;
+            if (fit_history) fit_history[0] = 1.0;
+            if (sweeps_done) *sweeps_done = 0;
+            ctx->stats = tucker_stats{};
+            ctx->stats.workspace_bytes = ctx->ws_bytes;
+            return;
+        }
+        if (init_factors) {
+            for (int n = 0; n < p.N; ++n) {
+                TK_HIP(hipMemcpyAsync(p.U32[n], init_factors[n], p.s[n] * p.R[n] * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+                TK_HIP(f32_to_f64(p.U32[n], p.U64[n], p.s[n] * p.R[n], s));
+            }
+        } else {
+            thosvd(r);
+        }
+        core_from_x(r);
+        core_norm_and_fit(r, p.fits + 0);
+        TK_HIP(hipEventRecord(ctx->ev[1], s));
+        int done = 0;
+        std::vector<double> hf(2);
+        for (int k = 1; k <= max_iters; ++k) {
+            if (p.tree)
+                sweep_tree(r);
+            else
+                sweep_generic(r);
+            core_norm_and_fit(r, p.fits + k);
+            done = k;
+            if (tol > 0.0) {
+                TK_HIP(hipMemcpyAsync(hf.data(), p.fits + k - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                TK_HIP(hipStreamSynchronize(s));
+                if (std::fabs(hf[1] - hf[0]) < tol) break;
+            }
+        }
+        TK_HIP(hipEventRecord(ctx->ev[2], s));
+        expand_chain(r, p.G, p.U32, nullptr, tensor);
+        TK_HIP(fit_from_resid(p.scal + 0, p.scal + 2, p.scal + 3, s));
+        TK_HIP(hipMemcpyAsync(core, p.G, prod(p.R, 0, p.N) * sizeof(float), hipMemcpyDeviceToDevice, s));
+        for (int n = 0; n < p.N; ++n)
+            TK_HIP(hipMemcpyAsync(factors[n], p.U32[n], p.s[n] * p.R[n] * sizeof(float), hipMemcpyDeviceToDevice, s));
+        TK_HIP(hipEventRecord(ctx->ev[3], s));
+        std::vector<double> fits(done + 1);
+        double fexact = 0.0;
+        int shifts = 0;
+        TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(&fexact, p.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(&shifts, p.shifts, sizeof(int), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        *fit = fexact;
+        if (fit_history)
+            for (int k = 0; k <= done; ++k) fit_history[k] = fits[k];
+        if (sweeps_done) *sweeps_done = done;
+        ctx->stats.init_ms = elapsed(ctx->ev[0], ctx->ev[1]);
+        ctx->stats.sweeps_ms = elapsed(ctx->ev[1], ctx->ev[2]);
+        ctx->stats.final_fit_ms = elapsed(ctx->ev[2], ctx->ev[3]);
+        ctx->stats.fit_gram = fits[done];
+        ctx->stats.sweeps = done;
+        ctx->stats.chol_shifts = shifts;
+        ctx->stats.workspace_bytes = ctx->ws_bytes;
+        if (!std::isfinite(fexact)) throw Fail{TUCKER_ERR_NUMERICAL, "non-finite fit"};
+    });
+}
+
+tucker_status tucker_decompose(tucker_ctx* ctx, const float* tensor, int ndim, const int64_t* dims,
+                               const int64_t* ranks, int max_iters, double tol, float* core, float* const* factors,
+                               double* fit, int* sweeps_done) {
+    return tucker_decompose_ex(ctx, tensor, ndim, dims, ranks, max_iters, tol, nullptr, core, factors, fit, nullptr,
+                               sweeps_done);
+}
+
+tucker_status tucker_reconstruct(tucker_ctx* ctx, const float* core, const float* const* factors, int ndim,
+                                 const int64_t* dims, const int64_t* ranks, float* out) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    ctx->err.clear();
+    std::string why;
+    tucker_status st = validate_args(ndim, dims, ranks, 0, 0.0, why);
+    if (st != TUCKER_OK) {
+        ctx->err = why;
+        return st;
+    }
+    if (!core || !factors || !out) return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (!factors[n]) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        make_plan(r.p, ndim, dims, ranks, 0);
+        bind(ctx, r.p);
+        float* U[TUCKER_MAX_ORDER];
+        for (int n = 0; n < ndim; ++n) U[n] = const_cast<float*>(factors[n]);
+        expand_chain(r, core, U, out, nullptr);
+    });
+}
+
+tucker_status tucker_ttm(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims, int mode, const float* U,
+                         int64_t rnew, float* out) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!in || !dims || !U || !out || ndim < 1 || ndim > TUCKER_MAX_ORDER || mode < 0 || mode >= ndim || rnew < 1)
+        return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (dims[n] < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        ttm(r, in, dims, ndim, mode, U, rnew, false, out);
+    });
+}
+
+tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims, int mode, float* out) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!in || !dims || !out || ndim < 1 || ndim > TUCKER_MAX_ORDER || mode < 0 || mode >= ndim)
+        return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (dims[n] < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        Plan& p = r.p;
+        const int64_t sdim = dims[mode];
+        const int64_t K = prod(dims, 0, ndim) / sdim;
+        with_scratch(ctx, [&](Arena& a) {
+            p.Fpart = a.take<double>(64 * 64 * 64);
+            p.S64 = a.take<double>(sdim <= kSmallMode ? sdim * sdim : 1);
+            p.P_elems = (int64_t)gram_splits(sdim, K) * sdim * sdim;
+            p.P = a.take<float>(sdim > kSmallMode ? p.P_elems : 1);
+        });
+        p.S32 = out;
+        gram(r, in, dims, ndim, mode, false);
+        if (sdim <= kSmallMode) TK_HIP(f64_to_f32(p.S64, out, sdim * sdim, r.st));
+    });
+}
+
+tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols, float* Q) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!Z || !Q || cols < 1 || rows < cols) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        Plan& p = r.p;
+        double* U64 = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            p.W = a.take<double>(cols * cols);
+            p.Wpart_elems = 16 * cols * cols;
+            p.Wpart = a.take<double>(p.Wpart_elems);
+            p.Tm = a.take<double>(cols * cols);
+            p.chol_ws = a.take<char>(chol_counter_ints(cols) * 4 + 64 + cols * 8);
+            p.Q1 = a.take<double>(rows * cols);
+            p.shifts = a.take<int>(4);
+            U64 = a.take<double>(rows * cols);
+        });
+        TK_HIP(fill_zero(p.shifts, 16, r.st));
+        orthonormalize(r, Z, rows, cols, U64, Q);
+    });
+}
+
+tucker_status tucker_gram_tn64(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols, double* W) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!Z || !W || cols < 1 || rows < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        Plan& p = r.p;
+        with_scratch(ctx, [&](Arena& a) {
+            p.Wpart_elems = 16 * cols * cols;
+            p.Wpart = a.take<double>(p.Wpart_elems);
+        });
+        gram_tn64(r, Z, true, rows, cols, W);
+    });
+}
+
+tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, double* T) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!W || !T || n < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        double* Wc = nullptr;
+        void* cw = nullptr;
+        int* shifts = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            Wc = a.take<double>(n * n);
+            cw = a.take<char>(chol_counter_ints(n) * 4 + 64 + n * 8);
+            shifts = a.take<int>(4);
+        });
+        TK_HIP(fill_zero(shifts, 16, ctx->stream));
+        TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        TK_HIP(chol_inv_scaled(Wc, n, true, T, (int*)cw, shifts, ctx->stream));
+        int sh = 0;
+        TK_HIP(hipMemcpyAsync(&sh, shifts, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        TK_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->stats.chol_shifts = sh;
+    });
+}
+
+tucker_status tucker_sym_eig(tucker_ctx* ctx, const float* S, int64_t n, int64_t rr, float* U, double* lam) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!S || !U || n < 1 || n > 64 || rr < 1 || rr > n) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        double *S64 = nullptr, *U64 = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            S64 = a.take<double>(n * n);
+            U64 = a.take<double>(n * rr);
+        });
+        TK_HIP(f32_to_f64(S, S64, n * n, ctx->stream));
+        TK_HIP(jacobi_eig(S64, (int)n, (int)rr, U64, U, lam, ctx->stream));
+    });
+}
+
+tucker_status tucker_sumsq(tucker_ctx* ctx, const float* x, int64_t n, double* result) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!x || !result || n < 0) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        double *red = nullptr, *out = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            red = a.take<double>(kSumsqBlocks);
+            out = a.take<double>(1);
+        });
+        TK_HIP(sumsq_f32(x, n, red, kSumsqBlocks, out, ctx->stream));
+        TK_HIP(hipMemcpyAsync(result, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        TK_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+const char* tucker_status_string(tucker_status s) {
+    switch (s) {
+        case TUCKER_OK: return "ok";
+        case TUCKER_ERR_INVALID_ARG: return "invalid argument";
+        case TUCKER_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case TUCKER_ERR_DEVICE: return "device error";
+        case TUCKER_ERR_NUMERICAL: return "numerical error";
+        case TUCKER_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* tucker_last_error(const tucker_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+tucker_status tucker_get_stats(const tucker_ctx* ctx, tucker_stats* out) {
+    if (!ctx || !out) return TUCKER_ERR_INVALID_ARG;
+    *out = ctx->stats;
+    return TUCKER_OK;
+}
+
+}  // extern "C"

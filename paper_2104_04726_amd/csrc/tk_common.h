@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of the Tucker-ALS library.
+// Every kernel launcher returns hipError_t and enqueues on the stream it is given.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tk {
+
+// ---------------------------------------------------------------------------------------
+// Strided operand descriptor.  Element (r, c) of a logical matrix lives at
+//   ptr[r * ld + (c / seg) * segstride + (c % seg)]
+// so one descriptor covers plain row-major matrices (seg >= #cols) and the (A, K, B)
+// views of a row-major tensor whose "column" index folds two modes (seg = B).
+// ---------------------------------------------------------------------------------------
+struct Desc {
+    const void* ptr;
+    int64_t ld;
+    int64_t seg;
+    int64_t segstride;
+};
+
+inline Desc plain(const void* p, int64_t ld) { return Desc{p, ld, int64_t(1) << 62, 0}; }
+inline Desc folded(const void* p, int64_t ld, int64_t seg, int64_t segstride) {
+    return Desc{p, ld, seg, segstride};
+}
+
+// Operand orientation: for A, KM means element (m,k) is desc(r=k, c=m); MK means desc(r=m, c=k).
+// For B, KN means (k,n) is desc(r=k, c=n); NK means desc(r=n, c=k).
+enum Orient { KM = 0, MK = 1 };
+
+enum Epilogue {
+    EPI_STORE = 0,      // C(m,n) = alpha * acc
+    EPI_ADD = 1,        // C(m,n) = alpha * acc + C(m,n)
+    EPI_RESID = 2       // sum over tile of (X(m,n) - alpha*acc)^2 into one double per block
+};
+
+struct GemmArgs {
+    Desc a, b, c;       // c: output (or, for EPI_RESID, the reference tensor X)
+    int64_t M, N, K;
+    double alpha;
+    int64_t k_split;    // K elements per split (grid.z splits); == K when not split
+    int64_t c_zstride;  // element offset between split outputs
+    int lower_only;     // enumerate only tiles with tile_m >= tile_n (Gram / SYRK)
+    double* resid_partial;   // EPI_RESID: one double per block
+};
+
+// fp32 MFMA GEMM (operands fp32, accumulation fp32; acc64 = FP64 accumulation across k-tiles)
+hipError_t gemm_f32(const GemmArgs& g, Orient oa, Orient ob, Epilogue epi, bool acc64,
+                    hipStream_t s);
+// fp64 MFMA GEMM; a_is_f32/b_is_f32 select float operands converted to double on load
+hipError_t gemm_f64(const GemmArgs& g, Orient oa, Orient ob, Epilogue epi, bool a_is_f32,
+                    bool b_is_f32, hipStream_t s);
+// number of blocks gemm_* launches for these arguments (for EPI_RESID partial sizing)
+int64_t gemm_grid_blocks(const GemmArgs& g, bool f64);
+
+// ---------------------------------------------------------------------------------------
+// Small / memory-bound kernels (tk_small.hip)
+// ---------------------------------------------------------------------------------------
+// partial[b] = sum of squares of a grid-stride share; then result = sum(partial) (fp64).
+hipError_t sumsq_f32(const float* x, int64_t n, double* partial, int nblocks, double* result,
+                     hipStream_t s);
+hipError_t sumsq_f64(const double* x, int64_t n, double* partial, int nblocks, double* result,
+                     hipStream_t s);
+hipError_t reduce_f64(const double* partial, int64_t n, double* result, hipStream_t s);
+constexpr int kSumsqBlocks = 1024;
+
+// Mode product on a (A, K, B) view with a small K and R:
+//   expand == false: out[a][r][b] = sum_k U[k*R + r] * in[a][k][b]   (U is K x R)
+//   expand == true : out[a][r][b] = sum_k U[r*K + k] * in[a][k][b]   (U is R x K)
+hipError_t small_ttm(const float* in, int64_t A, int64_t K, int64_t B, const float* U,
+                     int64_t R, bool expand, float* out, hipStream_t s);
+
+// Fused product over the two trailing modes of a (A, p, q) view (p <= 4, q <= 16):
+//   expand == false: out[a][r][t] = sum_{c,i} U3[c*R3+r] U4[i*R4+t] in[a][c][i]
+//   expand == true : out[a][c][i] = sum_{r,t} U3[c*R3+r] U4[i*R4+t] in[a][r][t]
+//   (U3 is p x R3, U4 is q x R4 in both cases)
+hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, int R3,
+                    const float* U4, int R4, bool expand, float* out, hipStream_t s);
+bool pair_ttm_supported(int p, int q);
+
+// Fibre Gram of a (A, L) row-major matrix (L <= 64): F = sum_a x_a x_a^T (fp64, L x L),
+// two-stage deterministic.  partial: nblocks * L * L doubles.
+hipError_t fibre_gram(const float* in, int64_t A, int L, double* partial, int nblocks,
+                      double* F, hipStream_t s);
+constexpr int kFibreGramBlocks = 512;
+
+// Given the fibre Gram F over (p x q) fibres and projectors P3 = U3 U3^T (p x p),
+// P4 = U4 U4^T (q x q) (fp64 factors), produce the mode Grams:
+//   which == 3: S3[c][c'] = sum_{i,i'} F[(c,i),(c',i')] P4[i][i']
+//   which == 4: S4[i][i'] = sum_{c,c'} F[(c,i),(c',i')] P3[c][c']
+// A null projector means the identity.  Output fp64 (n x n).
+hipError_t pair_mode_gram(const double* F, int p, int q, const double* U, int R, int which,
+                          double* S, hipStream_t s);
+
+// Mode Gram of a (A, s, B) view with s <= 64 by vector FMAs; fp64 result.
+hipError_t small_gram(const float* in, int64_t A, int64_t sdim, int64_t B, double* partial,
+                      int nblocks, double* S, hipStream_t s);
+
+// Split-K Gram reduction: S[i][j] = sum_z P[z][max(i,j)][min(i,j)] (fp64 sum, symmetric fill).
+hipError_t gram_reduce(const float* P, int nsplit, int64_t n, int64_t zstride, float* S32,
+                       double* S64, hipStream_t s);
+
+hipError_t f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
+hipError_t fill_identity_f32(float* out, int64_t rows, int64_t cols, hipStream_t s);
+hipError_t fill_identity_f64(double* out, int64_t rows, int64_t cols, hipStream_t s);
+hipError_t fill_zero(void* p, int64_t bytes, hipStream_t s);
+// counter-based start basis: out[i] = uniform(-1,1) from splitmix64(seed + i)
+hipError_t fill_random(float* out, int64_t n, uint64_t seed, hipStream_t s);
+// fit = 1 - sqrt(max(nx2 - ng2, 0)) / sqrt(nx2)   (single thread)
+hipError_t fit_from_norms(const double* nx2, const double* ng2, double* fit, hipStream_t s);
+hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Dense linear algebra (tk_linalg.hip)
+// ---------------------------------------------------------------------------------------
+// In place on W (n x n fp64, lower triangle read): column-scaled Cholesky W~ = D^-1 W D^-1 =
+// L L^T by a tiled task graph, then T = L^-1 D^-1 (lower triangular) written to Tout.
+// counters: int workspace of chol_counter_ints(n) entries (zeroed by the call).
+// shifts: int counter incremented for every pivot that needed the shifted fallback.
+hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double* Tout, int* counters,
+                           int* shifts, hipStream_t s);
+int64_t chol_counter_ints(int64_t n);
+
+// Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading
+// r eigenvectors (descending) to U64 (n x r fp64) and U32 (n x r fp32, nullable), all
+// eigenvalues descending to lam (nullable).
+hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam,
+                      hipStream_t s);
+
+}  // namespace tk

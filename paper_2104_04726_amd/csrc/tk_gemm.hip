@@ -1,0 +1,328 @@
+// Dense contractions of the HOOI sweep on CDNA4 matrix cores (gfx950).
+//
+// One kernel template computes C(m,n) = alpha * sum_k A(m,k) B(k,n) for operands described
+// by tk::Desc (row-major with an optional folded column index).  This single form covers
+// every dense contraction of a sweep (Sec. III-B, eq. (8) and the Gram of the text after it):
+//   * mode-n products  Y = T x_n U^T : A = U (KM), B = T viewed (A, s_n, B) (KN, folded);
+//   * mode-n Grams     S = Y_(n) Y_(n)^T : A = B = Y viewed (A, s_n, B) (MK/NK, folded k);
+//   * orthogonal iteration Z = S U, and the FP64 CholeskyQR products W = Z^T Z, Q = Z T^T.
+//
+// Tiling: 256 threads = 4 wave64s in a 2x2 grid; each wave owns a (BM/2) x (BN/2) block of
+// 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64).  Operand tiles are staged
+// through LDS in the orientation they have in memory ([k][m] for KM, [m][k] for MK), padded so
+// that the fragment reads of the 16x16x4 layout hit distinct banks.  The next k-tile is
+// prefetched into registers while the current one is multiplied.  Block ids are remapped so
+// that consecutive logical tiles (same N-tile, different M-tiles) run on the same XCD and share
+// its L2.
+#include "tk_common.h"
+
+namespace tk {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef f32x4 V;
+    static __device__ __forceinline__ V run(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef f64x4 V;
+    static __device__ __forceinline__ V run(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ __forceinline__ int64_t coloff(const Desc& d, int64_t c) {
+    return (c / d.seg) * d.segstride + (c % d.seg);
+}
+
+// logical tile index for hardware block b, so that each XCD gets a contiguous range
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    if (G < 16) return b;
+    const int64_t q = G / 8, r = G % 8;
+    const int64_t x = b % 8, idx = b / 8;
+    return x * q + (x < r ? x : r) + idx;
+}
+
+template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool ACC64, int BM, int BN,
+          int BK>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    constexpr int PADKM = (sizeof(T) == 4) ? 16 : 8;   // row stride of [k][x] tiles
+    constexpr int PADMK = (sizeof(T) == 4) ? 4 : 2;    // row stride of [x][k] tiles
+    constexpr int LDA = (OA == KM) ? (BM + PADKM) : (BK + PADMK);
+    constexpr int LDB = (OB == KM) ? (BN + PADKM) : (BK + PADMK);
+    constexpr int ASZ = (OA == KM) ? BK * LDA : BM * LDA;
+    constexpr int BSZ = (OB == KM) ? BK * LDB : BN * LDB;
+    constexpr int EA = BM * BK / 256;   // elements of A each thread loads per k-tile
+    constexpr int EB = BN * BK / 256;
+    constexpr int TM = BM / 32;         // 16x16 tiles per wave along m
+    constexpr int TN = BN / 32;
+    typedef typename Mfma<T>::V V;
+
+    __shared__ T As[ASZ];
+    __shared__ T Bs[BSZ];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    // ---- tile coordinates
+    const int64_t tilesM = (g.M + BM - 1) / BM;
+    const int64_t tilesN = (g.N + BN - 1) / BN;
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t tm, tn;
+    if (g.lower_only) {
+        tm = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+        while (tm * (tm + 1) / 2 > t) --tm;
+        tn = t - tm * (tm + 1) / 2;
+    } else {
+        tm = t % tilesM;
+        tn = t / tilesM;
+    }
+    if (tn >= tilesN || tm >= tilesM) return;
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.k_split;
+    const int64_t kend = (kbeg + g.k_split < g.K) ? kbeg + g.k_split : g.K;
+
+    const TA* __restrict__ pa = (const TA*)g.a.ptr;
+    const TB* __restrict__ pb = (const TB*)g.b.ptr;
+
+    // ---- per-thread load coordinates
+    // KM tile: BK rows (k) x BM cols (m): thread -> col c = tid % BM, rows r0 + step*u
+    // MK tile: BM rows (m) x BK cols (k): thread -> col c = tid % BK, rows r0 + step*u
+    const int a_c = (OA == KM) ? (tid % BM) : (tid % BK);
+    const int a_r0 = (OA == KM) ? (tid / BM) : (tid / BK);
+    constexpr int a_step = (OA == KM) ? (256 / BM) : (256 / BK);
+    const int b_c = (OB == KM) ? (tid % BN) : (tid % BK);
+    const int b_r0 = (OB == KM) ? (tid / BN) : (tid / BK);
+    constexpr int b_step = (OB == KM) ? (256 / BN) : (256 / BK);
+
+    // KM: the column (m or n) is fixed for the whole K loop
+    int64_t a_fix = 0, b_fix = 0;
+    bool a_colok = true, b_colok = true;
+    if (OA == KM) {
+        a_colok = (m0 + a_c) < g.M;
+        a_fix = a_colok ? coloff(g.a, m0 + a_c) : 0;
+    }
+    if (OB == KM) {
+        b_colok = (n0 + b_c) < g.N;
+        b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
+    }
+
+    T ra[EA], rb[EB];
+
+    auto load_tiles = [&](int64_t k0) {
+        if (OA == KM) {
+#pragma unroll
+            for (int u = 0; u < EA; ++u) {
+                const int64_t k = k0 + a_r0 + a_step * u;
+                ra[u] = (a_colok && k < kend) ? (T)pa[k * g.a.ld + a_fix] : (T)0;
+            }
+        } else {
+            const int64_t k = k0 + a_c;
+            const bool kok = k < kend;
+            const int64_t ko = kok ? coloff(g.a, k) : 0;
+#pragma unroll
+            for (int u = 0; u < EA; ++u) {
+                const int64_t m = m0 + a_r0 + a_step * u;
+                ra[u] = (kok && m < g.M) ? (T)pa[m * g.a.ld + ko] : (T)0;
+            }
+        }
+        if (OB == KM) {
+#pragma unroll
+            for (int u = 0; u < EB; ++u) {
+                const int64_t k = k0 + b_r0 + b_step * u;
+                rb[u] = (b_colok && k < kend) ? (T)pb[k * g.b.ld + b_fix] : (T)0;
+            }
+        } else {
+            const int64_t k = k0 + b_c;
+            const bool kok = k < kend;
+            const int64_t ko = kok ? coloff(g.b, k) : 0;
+#pragma unroll
+            for (int u = 0; u < EB; ++u) {
+                const int64_t n = n0 + b_r0 + b_step * u;
+                rb[u] = (kok && n < g.N) ? (T)pb[n * g.b.ld + ko] : (T)0;
+            }
+        }
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int u = 0; u < EA; ++u) As[(a_r0 + a_step * u) * LDA + a_c] = ra[u];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) Bs[(b_r0 + b_step * u) * LDB + b_c] = rb[u];
+    };
+
+    V acc[TM][TN];
+    double acc64[ACC64 ? TM : 1][ACC64 ? TN : 1][ACC64 ? 4 : 1];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            acc[i][j] = V{0, 0, 0, 0};
+            if (ACC64) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[ACC64 ? i : 0][ACC64 ? j : 0][ACC64 ? v : 0] = 0.0;
+            }
+        }
+
+    const int fr = lane & 15;       // row (m or n) inside a 16x16 tile
+    const int fk = lane >> 4;       // k inside a 4-wide k-step
+    const int wbm = wm * (BM / 2), wbn = wn * (BN / 2);
+
+    if (kbeg < kend) {
+        load_tiles(kbeg);
+        store_tiles();
+        __syncthreads();
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = (k0 + BK) < kend;
+            if (more) load_tiles(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                const int k = kk * 4 + fk;
+                T av[TM], bv[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int m = wbm + i * 16 + fr;
+                    av[i] = (OA == KM) ? As[k * LDA + m] : As[m * LDA + k];
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int n = wbn + j * 16 + fr;
+                    bv[j] = (OB == KM) ? Bs[k * LDB + n] : Bs[n * LDB + k];
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::run(av[i], bv[j], acc[i][j]);
+            }
+            if (ACC64) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc64[ACC64 ? i : 0][ACC64 ? j : 0][ACC64 ? v : 0] += (double)acc[i][j][v];
+                        acc[i][j] = V{0, 0, 0, 0};
+                    }
+            }
+            __syncthreads();
+            if (more) {
+                store_tiles();
+                __syncthreads();
+            }
+        }
+    }
+
+    // ---- epilogue.  16x16x4 output layout: lane holds column (lane & 15); its 4 accumulator
+    // entries are rows 4*(lane>>4)+v for the f32 instruction and rows (lane>>4)+4*v for f64.
+    T* __restrict__ pc = (T*)g.c.ptr + (int64_t)blockIdx.z * g.c_zstride;
+    double rsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wbn + j * 16 + fr;
+        if (n >= g.N) continue;
+        const int64_t co = coloff(g.c, n);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wbm + i * 16 + (sizeof(T) == 4 ? 4 * fk + v : fk + 4 * v);
+                if (m >= g.M) continue;
+                const double val =
+                    ACC64 ? acc64[ACC64 ? i : 0][ACC64 ? j : 0][ACC64 ? v : 0] : (double)acc[i][j][v];
+                T* dst = pc + m * g.c.ld + co;
+                if (EPI == EPI_STORE) {
+                    *dst = (T)(g.alpha * val);
+                } else if (EPI == EPI_ADD) {
+                    *dst = (T)(g.alpha * val + (double)*dst);
+                } else {
+                    const double d = (double)*dst - (double)(T)(g.alpha * val);
+                    rsum += d * d;
+                }
+            }
+        }
+    }
+    if (EPI == EPI_RESID) {
+        __shared__ double red[256];
+        red[tid] = rsum;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0)
+            g.resid_partial[(int64_t)blockIdx.z * gridDim.x + blockIdx.x] = red[0];
+    }
+}
+
+template <typename T, int BM, int BN>
+dim3 grid_of(const GemmArgs& g) {
+    const int64_t tilesM = (g.M + BM - 1) / BM;
+    const int64_t tilesN = (g.N + BN - 1) / BN;
+    const int64_t tiles = g.lower_only ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
+    const int64_t splits = (g.K + g.k_split - 1) / (g.k_split > 0 ? g.k_split : 1);
+    return dim3((unsigned)tiles, 1, (unsigned)(splits > 0 ? splits : 1));
+}
+
+template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool ACC64, int BM, int BN,
+          int BK>
+hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
+    dim3 grid = grid_of<T, BM, BN>(g);
+    if (grid.x == 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK>), grid, dim3(256), 0, s,
+                       g);
+    return hipGetLastError();
+}
+
+template <typename T, typename TA, typename TB, int EPI, bool ACC64, int BM, int BN, int BK>
+hipError_t by_orient(const GemmArgs& g, Orient oa, Orient ob, hipStream_t s) {
+    if (oa == KM && ob == KM) return launch_one<T, TA, TB, KM, KM, EPI, ACC64, BM, BN, BK>(g, s);
+    if (oa == KM && ob == MK) return launch_one<T, TA, TB, KM, MK, EPI, ACC64, BM, BN, BK>(g, s);
+    if (oa == MK && ob == KM) return launch_one<T, TA, TB, MK, KM, EPI, ACC64, BM, BN, BK>(g, s);
+    return launch_one<T, TA, TB, MK, MK, EPI, ACC64, BM, BN, BK>(g, s);
+}
+
+GemmArgs normalised(const GemmArgs& in) {
+    GemmArgs g = in;
+    if (g.k_split <= 0 || g.k_split > g.K) g.k_split = g.K > 0 ? g.K : 1;
+    return g;
+}
+
+}  // namespace
+
+int64_t gemm_grid_blocks(const GemmArgs& gin, bool f64) {
+    GemmArgs g = normalised(gin);
+    dim3 d = f64 ? grid_of<double, 64, 64>(g) : grid_of<float, 128, 128>(g);
+    return (int64_t)d.x * d.z;
+}
+
+hipError_t gemm_f32(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, bool acc64,
+                    hipStream_t s) {
+    GemmArgs g = normalised(gin);
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (epi == EPI_STORE)
+        return acc64 ? by_orient<float, float, float, EPI_STORE, true, 128, 128, 32>(g, oa, ob, s)
+                     : by_orient<float, float, float, EPI_STORE, false, 128, 128, 32>(g, oa, ob, s);
+    if (epi == EPI_ADD) return by_orient<float, float, float, EPI_ADD, false, 128, 128, 32>(g, oa, ob, s);
+    return by_orient<float, float, float, EPI_RESID, false, 128, 128, 32>(g, oa, ob, s);
+}
+
+hipError_t gemm_f64(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, bool a_is_f32,
+                    bool b_is_f32, hipStream_t s) {
+    GemmArgs g = normalised(gin);
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (epi != EPI_STORE) return hipErrorInvalidValue;
+    if (a_is_f32 && b_is_f32) return by_orient<double, float, float, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+    if (a_is_f32) return by_orient<double, float, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+    if (b_is_f32) return by_orient<double, double, float, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+    return by_orient<double, double, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+}
+
+}  // namespace tk

@@ -1,0 +1,411 @@
+// FP64 dense linear algebra for orthogonal iteration and the small modes (gfx950).
+//
+// chol_inv_scaled: W~ = D^-1 W D^-1 (D = sqrt(diag W)) is factored W~ = L L^T and T = L^-1 D^-1 is
+//   produced, so that Q = Z T^T has orthonormal columns when W = Z^T Z (one CholeskyQR pass).
+//   The n x n problem is split into 32 x 32 tiles and run as one launch of a tiled task graph:
+//   factor tasks (i,j), i >= j, in column-major order, then inverse tasks (i,j), i > j.
+//   Each workgroup claims the next task with an atomic ticket, so every task it waits for was
+//   claimed earlier by a running workgroup: the graph cannot deadlock whatever the residency.
+//   Waits are bounded spins; a timeout raises an error flag instead of hanging.
+//   Producer: stores, agent-scope fence, barrier, flag store-release.
+//   Consumer: flag load-acquire, barrier, agent-scope fence, loads.
+//
+// jacobi_eig: cyclic two-sided Jacobi (Golub & Van Loan, Alg. 8.4.3, with the parallel
+//   round-robin ordering) on a symmetric matrix of order <= 64 held in LDS.
+#include "tk_common.h"
+
+namespace tk {
+namespace {
+
+constexpr int TB = 32;
+constexpr int TS = 33;                      // padded LDS row stride
+constexpr long long kMaxSpin = 1ll << 24;   // bounded waits (x ~64 cycles of sleep each)
+
+struct CholArgs {
+    double* W;
+    int64_t n;
+    int T;
+    const double* dsc;     // 1/sqrt(W_ii) (or 1)
+    double* Tout;
+    int* ticket;
+    int* flagL;
+    int* flagI;
+    int* shifts;
+    int* err;
+};
+
+__device__ __forceinline__ int ld_acq(int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void wait_flags(int* f1, int* f2, int* err) {
+    if (threadIdx.x == 0) {
+        long long it = 0;
+        while ((ld_acq(f1) == 0 || (f2 && ld_acq(f2) == 0)) && it < kMaxSpin) {
+            __builtin_amdgcn_s_sleep(1);
+            ++it;
+        }
+        if (it >= kMaxSpin) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+__device__ void release_flag(int* f) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) st_rel(f, 1);
+}
+
+// tile (ti,tj) of an n x n row-major matrix -> LDS t; out-of-range -> 0 (or 1 on the diagonal
+// when pad_diag), optionally scaled by dsc[r] dsc[c]
+__device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dsc,
+                          bool pad_diag) {
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+        const int r = e / TB, c = e % TB;
+        const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
+        double v;
+        if (gr < n && gc < n) {
+            v = M[gr * n + gc];
+            if (dsc) v *= dsc[gr] * dsc[gc];
+        } else {
+            v = (pad_diag && gr == gc) ? 1.0 : 0.0;
+        }
+        t[r * TS + c] = v;
+    }
+}
+
+__device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t) {
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+        const int r = e / TB, c = e % TB;
+        const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
+        if (gr < n && gc < n) M[gr * n + gc] = t[r * TS + c];
+    }
+}
+
+// C = beta*C + alpha * A * op(B), op(B) = B^T when transB.  256 threads, 4 outputs each.
+__device__ void tile_gemm(double* C, const double* A, const double* B, bool transB, double alpha,
+                          double beta) {
+    const int r = threadIdx.x >> 3;
+    const int c0 = (threadIdx.x & 7) * 4;
+    double acc[4] = {0, 0, 0, 0};
+    for (int k = 0; k < TB; ++k) {
+        const double a = A[r * TS + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double b = transB ? B[(c0 + u) * TS + k] : B[k * TS + c0 + u];
+            acc[u] = fma(a, b, acc[u]);
+        }
+    }
+    __syncthreads();   // C may alias A or B
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        double* d = &C[r * TS + c0 + u];
+        *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[u];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-LDS Cholesky of a 32x32 tile (lower), by wave 0; lane i owns row i.  Pivots that are not
+// safely positive are replaced (shifted fallback) and counted.  Upper triangle is zeroed.
+__device__ void tile_potrf(double* A, int* shifts) {
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        for (int k = 0; k < TB; ++k) {
+            if (i == k) {
+                double d = A[k * TS + k];
+                if (!(d > 1e-13)) {
+                    d = 1e-13;
+                    atomicAdd(shifts, 1);
+                }
+                A[k * TS + k] = sqrt(d);
+            }
+            wave_sync();
+            const double piv = A[k * TS + k];
+            if (i > k && i < TB) A[i * TS + k] /= piv;
+            wave_sync();
+            if (i > k && i < TB) {
+                const double lik = A[i * TS + k];
+                for (int j = k + 1; j <= i; ++j) A[i * TS + j] -= lik * A[j * TS + k];
+            }
+            wave_sync();
+        }
+        if (i < TB)
+            for (int j = i + 1; j < TB; ++j) A[i * TS + j] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Inverse of a lower-triangular 32x32 tile L (LDS) into X (LDS); lane c computes column c.
+__device__ void tile_trtri(const double* L, double* X) {
+    if (threadIdx.x < TB) {
+        const int c = threadIdx.x;
+        double x[TB];
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= L[i * TS + k] * x[k];
+            x[i] = (i < c) ? 0.0 : s / L[i * TS + i];
+        }
+#pragma unroll
+        for (int i = 0; i < TB; ++i) X[i * TS + c] = x[i];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void chol_prologue(const double* W, int64_t n, bool scale, double* dsc,
+                                                    int* shifts) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double d = W[i * n + i];
+        if (!scale) {
+            dsc[i] = 1.0;
+        } else if (d > 0.0) {
+            dsc[i] = 1.0 / sqrt(d);
+        } else {
+            dsc[i] = 1.0;
+            atomicAdd(shifts, 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
+    __shared__ double At[TB * TS], Bt[TB * TS], Ct[TB * TS];
+    __shared__ int task_s;
+    if (threadIdx.x == 0) task_s = atomicAdd(a.ticket, 1);
+    __syncthreads();
+    const int task = task_s;
+    const int T = a.T;
+    const int nf = T * (T + 1) / 2;
+    if (task >= T * T) return;
+    auto fL = [&](int i, int j) { return a.flagL + i * T + j; };
+    auto fI = [&](int i, int j) { return a.flagI + i * T + j; };
+
+    if (task < nf) {
+        // column-major lower index -> (i, j)
+        int j = 0, rem = task;
+        while (rem >= T - j) {
+            rem -= T - j;
+            ++j;
+        }
+        const int i = j + rem;
+        load_tile(a.W, a.n, i, j, At, a.dsc, i == j);
+        for (int k = 0; k < j; ++k) {
+            wait_flags(fL(i, k), fL(j, k), a.err);
+            load_tile(a.W, a.n, i, k, Bt, nullptr, false);
+            if (i != j) load_tile(a.W, a.n, j, k, Ct, nullptr, false);
+            __syncthreads();
+            tile_gemm(At, Bt, (i != j) ? Ct : Bt, true, -1.0, 1.0);
+        }
+        if (i == j) {
+            tile_potrf(At, a.shifts);
+            tile_trtri(At, Bt);
+            store_tile(a.W, a.n, j, j, At);
+            store_tile(a.Tout, a.n, j, j, Bt);
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                st_rel(fL(j, j), 1);
+                st_rel(fI(j, j), 1);
+            }
+        } else {
+            wait_flags(fL(j, j), nullptr, a.err);
+            load_tile(a.Tout, a.n, j, j, Bt, nullptr, false);
+            __syncthreads();
+            tile_gemm(Ct, At, Bt, true, 1.0, 0.0);       // L_ij = A_ij Linv_jj^T
+            store_tile(a.W, a.n, i, j, Ct);
+            release_flag(fL(i, j));
+        }
+    } else {
+        int rem = task - nf, j = 0;
+        while (rem >= T - 1 - j) {
+            rem -= T - 1 - j;
+            ++j;
+        }
+        const int i = j + 1 + rem;
+        for (int e = threadIdx.x; e < TB * TS; e += blockDim.x) Ct[e] = 0.0;
+        __syncthreads();
+        for (int k = j; k < i; ++k) {
+            wait_flags(fL(i, k), fI(k, j), a.err);
+            load_tile(a.W, a.n, i, k, At, nullptr, false);
+            load_tile(a.Tout, a.n, k, j, Bt, nullptr, false);
+            __syncthreads();
+            tile_gemm(Ct, At, Bt, false, 1.0, 1.0);       // acc += L_ik Linv_kj
+        }
+        wait_flags(fI(i, i), nullptr, a.err);
+        load_tile(a.Tout, a.n, i, i, At, nullptr, false);
+        __syncthreads();
+        tile_gemm(Bt, At, Ct, false, -1.0, 0.0);          // Linv_ij = -Linv_ii acc
+        store_tile(a.Tout, a.n, i, j, Bt);
+        release_flag(fI(i, j));
+    }
+}
+
+// T <- lower(T) * D^-1 (column scaling), upper triangle zeroed
+__global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n, c = e % n;
+        Tm[e] = (r >= c) ? Tm[e] * dsc[c] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- Jacobi
+__global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ S, int n, int r,
+                                                     double* __restrict__ U64, float* __restrict__ U32,
+                                                     double* __restrict__ lam) {
+    constexpr int NM = 64, LD = 65;
+    __shared__ double A[NM * LD], V[NM * LD];
+    __shared__ double cs[NM / 2], sn[NM / 2];
+    __shared__ int pp[NM / 2], qq[NM / 2];
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int n2 = n + (n & 1);
+    for (int e = tid; e < n2 * n2; e += blockDim.x) {
+        const int i = e / n2, j = e % n2;
+        double v = 0.0;
+        if (i < n && j < n) v = 0.5 * (S[i * n + j] + S[j * n + i]);
+        A[i * LD + j] = v;
+        V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int npair = n2 / 2;
+    for (int sweep = 0; sweep < 40 && n2 > 1; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < n2 * n2; e += blockDim.x) {
+            const int i = e / n2, j = e % n2;
+            const double v = A[i * LD + j];
+            tot += v * v;
+            if (i != j) off += v * v;
+        }
+        red[tid] = off;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        const double offs = red[0];
+        __syncthreads();
+        red[tid] = tot;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        const double tots = red[0];
+        __syncthreads();
+        if (!(offs > 1e-30 * tots)) break;
+        for (int rr = 0; rr < n2 - 1; ++rr) {
+            if (tid < npair) {
+                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + rr) % (n2 - 1)); };
+                int p = player(tid), q = player(n2 - 1 - tid);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                const double apq = A[p * LD + q];
+                if (q < n && apq != 0.0) {
+                    const double app = A[p * LD + p], aqq = A[q * LD + q];
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                pp[tid] = p;
+                qq[tid] = q;
+                cs[tid] = c;
+                sn[tid] = s;
+            }
+            __syncthreads();
+            for (int e = tid; e < npair * n2; e += blockDim.x) {     // rows: A <- J^T A
+                const int k = e / n2, col = e % n2;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double ap = A[p * LD + col], aq = A[q * LD + col];
+                A[p * LD + col] = c * ap - s * aq;
+                A[q * LD + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            for (int e = tid; e < npair * n2; e += blockDim.x) {     // cols: A <- A J, V <- V J
+                const int k = e / n2, row = e % n2;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double ap = A[row * LD + p], aq = A[row * LD + q];
+                A[row * LD + p] = c * ap - s * aq;
+                A[row * LD + q] = s * ap + c * aq;
+                const double vp = V[row * LD + p], vq = V[row * LD + q];
+                V[row * LD + p] = c * vp - s * vq;
+                V[row * LD + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    // rank = number of larger eigenvalues (ties by index): descending order
+    __shared__ int rank[NM];
+    if (tid < n) {
+        const double li = A[tid * LD + tid];
+        int k = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j * LD + j];
+            if (lj > li || (lj == li && j < tid)) ++k;
+        }
+        rank[tid] = k;
+        if (lam) lam[k] = li;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int row = e / n, i = e % n;
+        const int k = rank[i];
+        if (k < r) {
+            const double v = V[row * LD + i];
+            U64[row * r + k] = v;
+            if (U32) U32[row * r + k] = (float)v;
+        }
+    }
+}
+
+}  // namespace
+
+int64_t chol_counter_ints(int64_t n) {
+    const int64_t T = (n + TB - 1) / TB;
+    return 2 + 2 * T * T;
+}
+
+hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double* Tout, int* counters, int* shifts,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int T = (int)((n + TB - 1) / TB);
+    // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); dsc stored after Tout?  no:
+    // the diagonal scale lives in the n doubles right after the counters (8-byte aligned).
+    hipError_t e = fill_zero(counters, chol_counter_ints(n) * (int64_t)sizeof(int), s);
+    if (e != hipSuccess) return e;
+    double* dsc = (double*)(((uintptr_t)(counters + chol_counter_ints(n)) + 15) & ~(uintptr_t)15);
+    hipLaunchKernelGGL(chol_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, scale, dsc, shifts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    CholArgs a{W, n, T, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1};
+    hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T)), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t total = n * n;
+    hipLaunchKernelGGL(chol_epilogue, dim3((unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096)),
+                       dim3(256), 0, s, Tout, n, dsc);
+    return hipGetLastError();
+}
+
+hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam, hipStream_t s) {
+    if (n < 1 || n > 64 || r < 1 || r > n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, s, S, n, r, U64, U32, lam);
+    return hipGetLastError();
+}
+
+}  // namespace tk

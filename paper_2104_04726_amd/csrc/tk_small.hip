@@ -1,0 +1,590 @@
+// Memory-bound and small-mode kernels of the HOOI sweep (gfx950, wave64).
+//
+//  * sumsq        ||x||^2 in FP64 by a fixed-grid two-stage tree (deterministic, no atomics):
+//                 ||X||^2 once and ||G||^2 per sweep for the fit.
+//  * pair_ttm     the full-tensor pass over the two trailing (small) modes:
+//                 T34 = X x_3 U3^T x_4 U4^T (eq. (8), the chain shared by modes 1 and 2),
+//                 the core G = T12 x_3 U3^T x_4 U4^T, and the expanding product of eq. (1).
+//                 Each block stages a contiguous run of fibres in LDS with coalesced 16-byte
+//                 loads; each thread maps one fibre through the two small factors held in LDS.
+//  * fibre_gram   sum over fibres of x x^T for fibres of length <= 64, from which the Grams of
+//                 both trailing modes follow for any U3/U4 (pair_mode_gram).
+//  * small_ttm / small_gram: one-mode products and Grams for modes of size <= 64.
+#include "tk_common.h"
+
+namespace tk {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_stage1(const T* __restrict__ x, int64_t n,
+                                                    double* __restrict__ partial) {
+    __shared__ double red[kThreads];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = (double)x[i];
+        acc += v * v;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// vectorised fp32 variant: 16-byte loads when x is 16-byte aligned
+__global__ __launch_bounds__(256) void sumsq_stage1_v4(const float4* __restrict__ x, int64_t n4,
+                                                       const float* __restrict__ tail, int ntail,
+                                                       double* __restrict__ partial) {
+    __shared__ double red[kThreads];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 v = x[i];
+        acc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) {
+        const double v = tail[threadIdx.x];
+        acc += v * v;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ partial, int64_t n,
+                                                     double* __restrict__ out) {
+    __shared__ double red[kThreads];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------- small one-mode product
+__global__ __launch_bounds__(256) void small_ttm_kernel(const float* __restrict__ in, int64_t A,
+                                                        int64_t K, int64_t B,
+                                                        const float* __restrict__ U, int64_t R,
+                                                        int expand, float* __restrict__ out) {
+    extern __shared__ float Us[];          // K*R factor entries, as Mk[k][r]
+    for (int64_t i = threadIdx.x; i < K * R; i += blockDim.x) {
+        const int64_t k = i / R, r = i % R;
+        Us[i] = expand ? U[r * K + k] : U[k * R + r];
+    }
+    __syncthreads();
+    const int64_t total = A * R * B;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += stride) {
+        const int64_t b = o % B;
+        const int64_t r = (o / B) % R;
+        const int64_t a = o / (B * R);
+        const float* src = in + a * K * B + b;
+        float acc = 0.f;
+        for (int64_t k = 0; k < K; ++k) acc = fmaf(Us[k * R + r], src[k * B], acc);
+        out[o] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- fused two-trailing-mode pass
+// Fibres are the (p x q) trailing blocks (contiguous, length L = p*q).  One block handles FPB
+// fibres per iteration; each thread one fibre.  LDS rows are padded to an odd stride.
+constexpr int kPairMaxP = 4, kPairMaxQ = 16;
+constexpr int kPairFPB = 256;
+
+template <bool EXPAND>
+__global__ __launch_bounds__(256) void pair_ttm_kernel(const float* __restrict__ in, int64_t A,
+                                                       int p, int q, const float* __restrict__ U3,
+                                                       int R3, const float* __restrict__ U4, int R4,
+                                                       float* __restrict__ out) {
+    // input fibre (len Lin) -> output fibre (len Lout)
+    const int Lin = EXPAND ? R3 * R4 : p * q;
+    const int Lout = EXPAND ? p * q : R3 * R4;
+    const int SIN = Lin | 1, SOUT = Lout | 1;     // odd strides: conflict-free column access
+    extern __shared__ float lds[];
+    float* u3 = lds;                              // p x R3
+    float* u4 = u3 + kPairMaxP * kPairMaxP;       // q x R4
+    float* fin = u4 + kPairMaxQ * kPairMaxQ;      // FPB x SIN
+    float* fout = fin + kPairFPB * SIN;           // FPB x SOUT
+    for (int i = threadIdx.x; i < p * R3; i += blockDim.x) u3[i] = U3[i];
+    for (int i = threadIdx.x; i < q * R4; i += blockDim.x) u4[i] = U4[i];
+
+    const int64_t nchunks = (A + kPairFPB - 1) / kPairFPB;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t f0 = ch * kPairFPB;
+        const int nf = (int)((A - f0) < kPairFPB ? (A - f0) : kPairFPB);
+        const int64_t nin = (int64_t)nf * Lin;
+        const float* src = in + f0 * Lin;
+        __syncthreads();
+        // coalesced copy of nf fibres into padded LDS rows
+        if ((((uintptr_t)src) & 15) == 0) {
+            const int64_t n4 = nin / 4;
+            const float4* s4 = (const float4*)src;
+            for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
+                const float4 v = s4[i];
+                const int64_t e = i * 4;
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t g = e + j;
+                    fin[(g / Lin) * SIN + (g % Lin)] = vv[j];
+                }
+            }
+            for (int64_t g = n4 * 4 + threadIdx.x; g < nin; g += blockDim.x)
+                fin[(g / Lin) * SIN + (g % Lin)] = src[g];
+        } else {
+            for (int64_t g = threadIdx.x; g < nin; g += blockDim.x)
+                fin[(g / Lin) * SIN + (g % Lin)] = src[g];
+        }
+        __syncthreads();
+        const int f = threadIdx.x;
+        if (f < nf) {
+            const float* x = fin + f * SIN;
+            float* y = fout + f * SOUT;
+            if (!EXPAND) {
+                // tmp[c][t] = sum_i x[c][i] U4[i][t];  y[r][t] = sum_c U3[c][r] tmp[c][t]
+                float tmp[kPairMaxP][kPairMaxQ];
+#pragma unroll
+                for (int c = 0; c < kPairMaxP; ++c) {
+                    if (c >= p) break;
+#pragma unroll
+                    for (int t = 0; t < kPairMaxQ; ++t) {
+                        if (t >= R4) break;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int i = 0; i < kPairMaxQ; ++i) {
+                            if (i >= q) break;
+                            acc = fmaf(x[c * q + i], u4[i * R4 + t], acc);
+                        }
+                        tmp[c][t] = acc;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kPairMaxP; ++r) {
+                    if (r >= R3) break;
+#pragma unroll
+                    for (int t = 0; t < kPairMaxQ; ++t) {
+                        if (t >= R4) break;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int c = 0; c < kPairMaxP; ++c) {
+                            if (c >= p) break;
+                            acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                        }
+                        y[r * R4 + t] = acc;
+                    }
+                }
+            } else {
+                // tmp[r][i] = sum_t x[r][t] U4[i][t];  y[c][i] = sum_r U3[c][r] tmp[r][i]
+                float tmp[kPairMaxP][kPairMaxQ];
+#pragma unroll
+                for (int r = 0; r < kPairMaxP; ++r) {
+                    if (r >= R3) break;
+#pragma unroll
+                    for (int i = 0; i < kPairMaxQ; ++i) {
+                        if (i >= q) break;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int t = 0; t < kPairMaxQ; ++t) {
+                            if (t >= R4) break;
+                            acc = fmaf(x[r * R4 + t], u4[i * R4 + t], acc);
+                        }
+                        tmp[r][i] = acc;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < kPairMaxP; ++c) {
+                    if (c >= p) break;
+#pragma unroll
+                    for (int i = 0; i < kPairMaxQ; ++i) {
+                        if (i >= q) break;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int r = 0; r < kPairMaxP; ++r) {
+                            if (r >= R3) break;
+                            acc = fmaf(u3[c * R3 + r], tmp[r][i], acc);
+                        }
+                        y[c * q + i] = acc;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // coalesced write-back
+        const int64_t nout = (int64_t)nf * Lout;
+        float* dst = out + f0 * Lout;
+        for (int64_t g = threadIdx.x; g < nout; g += blockDim.x) dst[g] = fout[(g / Lout) * SOUT + (g % Lout)];
+    }
+}
+
+// ---------------------------------------------------------------- fibre Gram (L <= 64)
+// Each block accumulates the lower triangle of sum_a x_a x_a^T over its share of fibres,
+// staged through LDS 64 fibres at a time; thread -> fixed set of (i,j) pairs.
+constexpr int kFG_FPB = 64;
+__global__ __launch_bounds__(256) void fibre_gram_kernel(const float* __restrict__ in, int64_t A, int L,
+                                                         double* __restrict__ partial) {
+    __shared__ float xs[kFG_FPB * 65];
+    const int npairs = L * (L + 1) / 2;
+    const int per = (npairs + blockDim.x - 1) / blockDim.x;   // <= 9 for L = 64
+    int pi[9], pj[9];
+    float acc[9];
+    for (int u = 0; u < 9; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        int i = 0, j = 0;
+        if (u < per && idx < npairs) {
+            i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+            while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+            while (i * (i + 1) / 2 > idx) --i;
+            j = idx - i * (i + 1) / 2;
+        } else {
+            i = -1;
+        }
+        pi[u] = i;
+        pj[u] = j;
+        acc[u] = 0.f;
+    }
+    double accd[9];
+    for (int u = 0; u < 9; ++u) accd[u] = 0.0;
+    const int64_t nchunks = (A + kFG_FPB - 1) / kFG_FPB;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t f0 = ch * kFG_FPB;
+        const int nf = (int)((A - f0) < kFG_FPB ? (A - f0) : kFG_FPB);
+        __syncthreads();
+        for (int g = threadIdx.x; g < nf * L; g += blockDim.x) xs[(g / L) * 65 + (g % L)] = in[f0 * L + g];
+        __syncthreads();
+        for (int u = 0; u < 9; ++u) {
+            if (pi[u] < 0) continue;
+            float a = 0.f;
+            for (int f = 0; f < nf; ++f) a = fmaf(xs[f * 65 + pi[u]], xs[f * 65 + pj[u]], a);
+            accd[u] += (double)a;      // FP64 across chunks of 64 fibres
+        }
+    }
+    double* dst = partial + (int64_t)blockIdx.x * L * L;
+    for (int u = 0; u < 9; ++u) {
+        if (pi[u] < 0) continue;
+        dst[pi[u] * L + pj[u]] = accd[u];
+    }
+    (void)acc;
+}
+
+__global__ __launch_bounds__(256) void fibre_gram_reduce(const double* __restrict__ partial, int nblocks,
+                                                         int L, double* __restrict__ F) {
+    const int npairs = L * (L + 1) / 2;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < npairs; idx += gridDim.x * blockDim.x) {
+        int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+        while (i * (i + 1) / 2 > idx) --i;
+        const int j = idx - i * (i + 1) / 2;
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * L * L + i * L + j];
+        F[i * L + j] = s;
+        F[j * L + i] = s;
+    }
+}
+
+// S3/S4 from the fibre Gram and the projector of the other trailing mode
+__global__ __launch_bounds__(256) void pair_mode_gram_kernel(const double* __restrict__ F, int p, int q,
+                                                             const double* __restrict__ U, int R,
+                                                             int which, double* __restrict__ S) {
+    const int L = p * q;
+    const int n = (which == 3) ? p : q;
+    const int o = (which == 3) ? q : p;      // size of the other mode
+    __shared__ double P[64 * 64];
+    for (int e = threadIdx.x; e < o * o; e += blockDim.x) {
+        const int a = e / o, b = e % o;
+        double v = 0.0;
+        if (U) {
+            for (int r = 0; r < R; ++r) v += U[a * R + r] * U[b * R + r];
+        } else {
+            v = (a == b) ? 1.0 : 0.0;
+        }
+        P[e] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int x = e / n, y = e % n;
+        double acc = 0.0;
+        for (int a = 0; a < o; ++a)
+            for (int b = 0; b < o; ++b) {
+                const double pv = P[a * o + b];
+                if (pv == 0.0) continue;
+                // which==3: F[(x,a),(y,b)]  (fibre index c*q+i);  which==4: F[(a,x),(b,y)]
+                const int r = (which == 3) ? x * q + a : a * q + x;
+                const int c = (which == 3) ? y * q + b : b * q + y;
+                acc += F[r * L + c] * pv;
+            }
+        S[e] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- small Gram (s <= 64)
+// S[i][j] = sum_{a,b} Y[a][i][b] Y[a][j][b]; each block takes a range of (a, b) columns.
+__global__ __launch_bounds__(256) void small_gram_kernel(const float* __restrict__ in, int64_t A,
+                                                         int64_t sdim, int64_t B,
+                                                         double* __restrict__ partial) {
+    __shared__ float cs[64 * 65];     // 64 columns x sdim rows, column-major with stride 65
+    const int s = (int)sdim;
+    const int npairs = s * (s + 1) / 2;
+    int pi[9], pj[9];
+    double accd[9];
+    for (int u = 0; u < 9; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        if (idx < npairs) {
+            int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+            while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+            while (i * (i + 1) / 2 > idx) --i;
+            pi[u] = i;
+            pj[u] = idx - i * (i + 1) / 2;
+        } else {
+            pi[u] = -1;
+            pj[u] = 0;
+        }
+        accd[u] = 0.0;
+    }
+    const int64_t ncols = A * B;
+    const int64_t nchunks = (ncols + 63) / 64;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t c0 = ch * 64;
+        const int nc = (int)((ncols - c0) < 64 ? (ncols - c0) : 64);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc * s; e += blockDim.x) {
+            const int cc = e % nc, i = e / nc;
+            const int64_t col = c0 + cc;
+            const int64_t a = col / B, b = col % B;
+            cs[cc * 65 + i] = in[(a * sdim + i) * B + b];
+        }
+        __syncthreads();
+        for (int u = 0; u < 9; ++u) {
+            if (pi[u] < 0) continue;
+            float acc = 0.f;
+            for (int cc = 0; cc < nc; ++cc) acc = fmaf(cs[cc * 65 + pi[u]], cs[cc * 65 + pj[u]], acc);
+            accd[u] += (double)acc;
+        }
+    }
+    double* dst = partial + (int64_t)blockIdx.x * s * s;
+    for (int u = 0; u < 9; ++u)
+        if (pi[u] >= 0) dst[pi[u] * s + pj[u]] = accd[u];
+}
+
+// ---------------------------------------------------------------- split-K Gram reduction
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const float* __restrict__ P, int nsplit,
+                                                          int64_t n, int64_t zstride,
+                                                          float* __restrict__ S32,
+                                                          double* __restrict__ S64) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
+        double s = 0.0;
+        for (int z = 0; z < nsplit; ++z) s += (double)P[z * zstride + src];
+        if (S32) S32[e] = (float)s;
+        if (S64) S64[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------- elementwise helpers
+__global__ void f64_to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+__global__ void f32_to_f64_kernel(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
+}
+template <typename T>
+__global__ void identity_kernel(T* __restrict__ out, int64_t rows, int64_t cols) {
+    const int64_t n = rows * cols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (i / cols == i % cols) ? (T)1 : (T)0;
+}
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+// SplitMix64 (Steele, Lea & Flood, 2014): a counter-based 64-bit mixer.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ void random_kernel(float* __restrict__ out, int64_t n, uint64_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t h = splitmix64(seed + (uint64_t)i);
+        out[i] = (float)((double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+    }
+}
+__global__ void fit_norms_kernel(const double* nx2, const double* ng2, double* fit) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double a = *nx2;
+        if (!(a > 0.0)) {
+            *fit = 1.0;
+            return;
+        }
+        const double d = a - *ng2;
+        *fit = 1.0 - sqrt(d > 0.0 ? d : 0.0) / sqrt(a);
+    }
+}
+__global__ void fit_resid_kernel(const double* nx2, const double* r2, double* fit) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double a = *nx2;
+        *fit = (a > 0.0) ? 1.0 - sqrt(*r2 > 0.0 ? *r2 : 0.0) / sqrt(a) : 1.0;
+    }
+}
+
+unsigned grid_for(int64_t n, int64_t cap = 4096) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t sumsq_f32(const float* x, int64_t n, double* partial, int nblocks, double* result,
+                     hipStream_t s) {
+    if ((((uintptr_t)x) & 15) == 0 && n >= 4) {
+        const int64_t n4 = n / 4;
+        const int ntail = (int)(n - n4 * 4);
+        hipLaunchKernelGGL(sumsq_stage1_v4, dim3(nblocks), dim3(kThreads), 0, s, (const float4*)x, n4,
+                           x + n4 * 4, ntail, partial);
+    } else {
+        hipLaunchKernelGGL(sumsq_stage1<float>, dim3(nblocks), dim3(kThreads), 0, s, x, n, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_f64(partial, nblocks, result, s);
+}
+
+hipError_t sumsq_f64(const double* x, int64_t n, double* partial, int nblocks, double* result,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(sumsq_stage1<double>, dim3(nblocks), dim3(kThreads), 0, s, x, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_f64(partial, nblocks, result, s);
+}
+
+hipError_t reduce_f64(const double* partial, int64_t n, double* result, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, partial, n, result);
+    return hipGetLastError();
+}
+
+hipError_t small_ttm(const float* in, int64_t A, int64_t K, int64_t B, const float* U, int64_t R,
+                     bool expand, float* out, hipStream_t s) {
+    const int64_t total = A * R * B;
+    if (total == 0) return hipSuccess;
+    const size_t shm = (size_t)K * R * sizeof(float);
+    hipLaunchKernelGGL(small_ttm_kernel, dim3(grid_for(total, 8192)), dim3(256), shm, s, in, A, K, B, U, R,
+                       expand ? 1 : 0, out);
+    return hipGetLastError();
+}
+
+bool pair_ttm_supported(int p, int q) { return p >= 1 && p <= kPairMaxP && q >= 1 && q <= kPairMaxQ; }
+
+hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, int R3, const float* U4,
+                    int R4, bool expand, float* out, hipStream_t s) {
+    if (!pair_ttm_supported(p, q) || R3 > p || R4 > q) return hipErrorInvalidValue;
+    if (A == 0) return hipSuccess;
+    const int Lin = expand ? R3 * R4 : p * q;
+    const int Lout = expand ? p * q : R3 * R4;
+    const size_t shm = sizeof(float) * (kPairMaxP * kPairMaxP + kPairMaxQ * kPairMaxQ +
+                                        (size_t)kPairFPB * ((Lin | 1) + (Lout | 1)));
+    const int64_t nchunks = (A + kPairFPB - 1) / kPairFPB;
+    const unsigned grid = (unsigned)(nchunks < 2048 ? nchunks : 2048);
+    hipError_t e;
+    if (expand) {
+        e = hipFuncSetAttribute((const void*)pair_ttm_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pair_ttm_kernel<true>, dim3(grid), dim3(256), shm, s, in, A, p, q, U3, R3, U4, R4, out);
+    } else {
+        e = hipFuncSetAttribute((const void*)pair_ttm_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pair_ttm_kernel<false>, dim3(grid), dim3(256), shm, s, in, A, p, q, U3, R3, U4, R4, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t fibre_gram(const float* in, int64_t A, int L, double* partial, int nblocks, double* F,
+                      hipStream_t s) {
+    if (L < 1 || L > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fibre_gram_kernel, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fibre_gram_reduce, dim3(grid_for(L * (L + 1) / 2, 64)), dim3(256), 0, s, partial,
+                       nblocks, L, F);
+    return hipGetLastError();
+}
+
+hipError_t pair_mode_gram(const double* F, int p, int q, const double* U, int R, int which, double* S,
+                          hipStream_t s) {
+    if (p * q > 64 || (which != 3 && which != 4)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pair_mode_gram_kernel, dim3(1), dim3(256), 0, s, F, p, q, U, R, which, S);
+    return hipGetLastError();
+}
+
+hipError_t small_gram(const float* in, int64_t A, int64_t sdim, int64_t B, double* partial, int nblocks,
+                      double* S, hipStream_t s) {
+    if (sdim < 1 || sdim > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(small_gram_kernel, dim3(nblocks), dim3(256), 0, s, in, A, sdim, B, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fibre_gram_reduce, dim3(grid_for(sdim * (sdim + 1) / 2, 64)), dim3(256), 0, s, partial,
+                       nblocks, (int)sdim, S);
+    return hipGetLastError();
+}
+
+hipError_t gram_reduce(const float* P, int nsplit, int64_t n, int64_t zstride, float* S32, double* S64,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(n * n, 4096)), dim3(256), 0, s, P, nsplit, n, zstride,
+                       S32, S64);
+    return hipGetLastError();
+}
+
+hipError_t f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(f32_to_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t fill_identity_f32(float* out, int64_t rows, int64_t cols, hipStream_t s) {
+    hipLaunchKernelGGL(identity_kernel<float>, dim3(grid_for(rows * cols)), dim3(256), 0, s, out, rows, cols);
+    return hipGetLastError();
+}
+hipError_t fill_identity_f64(double* out, int64_t rows, int64_t cols, hipStream_t s) {
+    hipLaunchKernelGGL(identity_kernel<double>, dim3(grid_for(rows * cols)), dim3(256), 0, s, out, rows, cols);
+    return hipGetLastError();
+}
+hipError_t fill_zero(void* p, int64_t bytes, hipStream_t s) {
+    const int64_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(256), 0, s, (uint32_t*)p, n);
+    return hipGetLastError();
+}
+hipError_t fill_random(float* out, int64_t n, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(random_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, n, seed);
+    return hipGetLastError();
+}
+hipError_t fit_from_norms(const double* nx2, const double* ng2, double* fit, hipStream_t s) {
+    hipLaunchKernelGGL(fit_norms_kernel, dim3(1), dim3(64), 0, s, nx2, ng2, fit);
+    return hipGetLastError();
+}
+hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipStream_t s) {
+    hipLaunchKernelGGL(fit_resid_kernel, dim3(1), dim3(64), 0, s, nx2, r2, fit);
+    return hipGetLastError();
+}
+
+}  // namespace tk

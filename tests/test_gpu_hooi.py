@@ -1,0 +1,199 @@
+"""End-to-end parity of the GPU HOOI with the FP64 oracle (needs an MI355X).
+
+Both sides run on the same float32 input (the oracle on its exact float64 value).  Results
+are compared through rotation-invariant quantities (oracle.compare):
+
+* fit, rho = 1 - fit, core norm: <= 1e-5 (the FP32-path tolerance of the method);
+* reconstruction difference and largest principal-angle sine: <= 1e-5 where the spectra
+  are gapped (exact-rank inputs); on image stacks the subspace next to the rank boundary
+  is not determined by FP32 data, so those two carry the perturbation bound
+  sin theta <= ||dS|| / gap (Davis-Kahan) with an FP32 Gram error budget ||dS|| <= 1e-6 lam_1,
+  i.e. sin theta_n <= max(1e-5, 1e-6 g_n), g_n = lam_1 / (lam_R - lam_{R+1}), and the
+  reconstruction bound max(1e-5, 2e-6 sum_n g_n sqrt(lam_R / lam_1)).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_exact_rank, make_stereo_stack, make_tiny, STACK_CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2104_04726_amd as tk
+    c = tk.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _gpu(ctx, x32, ranks, iters, **kw):
+    res = ctx.decompose(_dev(x32), ranks, iters, **kw)
+    return dict(core=res.core.cpu().numpy().astype(np.float64),
+                factors=[u.cpu().numpy().astype(np.float64) for u in res.factors],
+                fit=res.fit, hist=res.fit_history, sweeps=res.sweeps, stats=res.stats)
+
+
+def _ora(x32, ranks, iters, **kw):
+    r = oracle.hooi(x32.astype(np.float64), ranks, iters, **kw)
+    return dict(core=r.core, factors=r.factors, fit=r.fits[-1], res=r)
+
+
+def _check_strict(m, tol=1e-5):
+    assert m["fit"] <= tol, m
+    assert m["core_norm"] <= tol, m
+    assert m["recon"] <= tol, m
+    assert max(m["sin_theta"]) <= tol, m
+    assert max(m["orth"]) <= tol, m
+
+
+# ------------------------------------------------------------------ tiny exact-rank cases
+
+@pytest.mark.parametrize("iters", [0, 1, 10])
+def test_tiny_matches_oracle(ctx, iters):
+    x, _, _ = make_tiny(0, 1e-3)
+    x32 = x.astype(np.float32)
+    _say(f"tiny iters={iters}")
+    g = _gpu(ctx, x32, (16, 12, 3, 4), iters)
+    o = _ora(x32, (16, 12, 3, 4), iters)
+    _check_strict(oracle.compare(g, o))
+    assert g["sweeps"] == iters
+    # the per-sweep fit history (||G||-based) tracks the oracle's
+    for a, b in zip(g["hist"], o["res"].fits):
+        assert abs(a - b) <= 1e-4
+
+
+def test_tiny_exact_rank_recovery(ctx):
+    x, core, fac = make_tiny(0, 0.0)
+    _say("tiny exact rank")
+    g = _gpu(ctx, x.astype(np.float32), (16, 12, 3, 4), 3)
+    assert g["fit"] >= 1.0 - 1e-5
+    for u, t in zip(g["factors"], fac):
+        assert oracle.sin_theta_max(u, t) <= 1e-5
+
+
+@pytest.mark.parametrize("dims,ranks,iters", [
+    ((100, 90, 80), (10, 9, 8), 4),              # order 3, large modes: OI, direct chains
+    ((8, 7, 6, 5, 4), (3, 3, 2, 2, 2), 5),        # order 5, small modes
+    ((130, 70, 5, 4), (12, 10, 3, 2), 5),         # order 4 tree with one large mode
+    ((96, 80, 2, 9), (20, 16, 2, 5), 5),          # tree, R3 = s3
+])
+def test_exact_rank_orders(ctx, dims, ranks, iters):
+    x, _, _ = make_exact_rank(dims, ranks, seed=3, noise_rel=1e-3)
+    x32 = x.astype(np.float32)
+    _say(f"exact-rank dims={dims}")
+    g = _gpu(ctx, x32, ranks, iters)
+    o = _ora(x32, ranks, iters)
+    _check_strict(oracle.compare(g, o))
+
+
+def test_order2_eckart_young(ctx):
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal((300, 40)) @ np.diag(np.geomspace(10, 0.1, 40)) @ rng.standard_normal((40, 200)))
+    x32 = x.astype(np.float32)
+    _say("order 2")
+    g = _gpu(ctx, x32, (20, 20), 2)
+    s = np.linalg.svd(x32.astype(np.float64), compute_uv=False)
+    expected = 1.0 - math.sqrt(float(np.sum(s[20:] ** 2))) / math.sqrt(float(np.sum(s ** 2)))
+    assert abs(g["fit"] - expected) <= 1e-5
+
+
+# ------------------------------------------------------------------ image stacks
+
+def _gap_bounds(o, ranks):
+    res = o["res"]
+    g = [res.gap_factor(n, r) for n, r in enumerate(ranks)]
+    lam = res.spectra
+    sin_tol, h = [], 0.0
+    for n, r in enumerate(ranks):
+        if r >= len(lam[n]):
+            sin_tol.append(1e-5)
+            continue
+        sin_tol.append(max(1e-5, 1e-6 * g[n]))
+        h += g[n] * math.sqrt(max(lam[n][r - 1], 0.0) / lam[n][0])
+    return sin_tol, max(1e-5, 2e-6 * h)
+
+
+@pytest.mark.parametrize("name", ["stack_mini", "stack_mini_ipt"])
+def test_stack_matches_oracle(ctx, name):
+    c = STACK_CONFIGS[name]
+    x32 = make_stereo_stack(c["H"], c["W"], c["E"], c["colorspace"], c["seed"])
+    ranks, iters = c["ranks"], c["sweeps"]
+    _say(f"stack {name}")
+    g = _gpu(ctx, x32, ranks, iters)
+    o = _ora(x32, ranks, iters)
+    m = oracle.compare(g, o)
+    sin_tol, recon_tol = _gap_bounds(o, ranks)
+    _say(f"  metrics {m}")
+    assert m["fit"] <= 1e-5 and m["rho"] <= 1e-5 and m["core_norm"] <= 1e-5, m
+    assert m["recon"] <= recon_tol, (m, recon_tol)
+    for st, tol in zip(m["sin_theta"], sin_tol):
+        assert st <= tol
+    assert max(m["orth"]) <= 1e-5
+
+
+# ------------------------------------------------------------------ API behaviour
+
+def test_resume_equals_longer_run(ctx):
+    x, _, _ = make_exact_rank((70, 66, 3, 5), (12, 10, 3, 3), seed=5, noise_rel=1e-2)
+    x32 = x.astype(np.float32)
+    _say("resume")
+    full = ctx.decompose(_dev(x32), (12, 10, 3, 3), 5)
+    part = ctx.decompose(_dev(x32), (12, 10, 3, 3), 2)
+    rest = ctx.decompose(_dev(x32), (12, 10, 3, 3), 3, init_factors=part.factors)
+    a = dict(core=full.core.cpu().numpy(), factors=[u.cpu().numpy() for u in full.factors], fit=full.fit)
+    b = dict(core=rest.core.cpu().numpy(), factors=[u.cpu().numpy() for u in rest.factors], fit=rest.fit)
+    _check_strict(oracle.compare(a, b))
+
+
+def test_reconstruct_matches_definition(ctx):
+    rng = np.random.default_rng(4)
+    dims, ranks = (150, 90, 3, 6), (20, 30, 2, 4)
+    core = rng.standard_normal(ranks).astype(np.float32)
+    facs = [np.linalg.qr(rng.standard_normal((s, r)))[0].astype(np.float32) for s, r in zip(dims, ranks)]
+    _say("reconstruct")
+    got = ctx.reconstruct(_dev(core), [_dev(u) for u in facs]).cpu().numpy().astype(np.float64)
+    ref = oracle.reconstruct(core.astype(np.float64), [u.astype(np.float64) for u in facs])
+    assert got.shape == dims
+    assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_deterministic(ctx):
+    x, _, _ = make_tiny(1, 1e-3)
+    x32 = x.astype(np.float32)
+    _say("determinism")
+    a = ctx.decompose(_dev(x32), (16, 12, 3, 4), 4)
+    b = ctx.decompose(_dev(x32), (16, 12, 3, 4), 4)
+    assert a.fit == b.fit
+    assert np.array_equal(a.core.cpu().numpy(), b.core.cpu().numpy())
+
+
+def test_zero_and_nonfinite_inputs(ctx):
+    import paper_2104_04726_amd as tk
+    _say("zero / nan")
+    z = np.zeros((10, 9, 3, 4), dtype=np.float32)
+    r = ctx.decompose(_dev(z), (3, 3, 2, 2), 3)
+    assert r.fit == 1.0 and not np.any(r.core.cpu().numpy())
+    for u, (s, k) in zip(r.factors, [(10, 3), (9, 3), (3, 2), (4, 2)]):
+        assert np.array_equal(u.cpu().numpy(), np.eye(s, k, dtype=np.float32))
+    bad = np.ones((10, 9, 3, 4), dtype=np.float32)
+    bad[1, 2, 0, 3] = np.nan
+    with pytest.raises(tk.TuckerError) as ei:
+        ctx.decompose(_dev(bad), (3, 3, 2, 2), 3)
+    assert ei.value.code == 4
+    with pytest.raises(tk.TuckerError) as ei:
+        ctx.decompose(_dev(z), (11, 3, 2, 2), 3)
+    assert ei.value.code == 1
