@@ -68,7 +68,26 @@ typedef struct {
     int use_graphs;              /* reserved (0)                                              */
     size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
     uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
+    int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats)   */
 } tucker_options;
+
+/* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack
+ * X (s1 x s2 x s3 x s4) with small trailing modes; single-kernel stages are marked *). */
+typedef enum {
+    TUCKER_STAGE_PASS_A = 0,     /* * T34 = X x3 U3^T x4 U4^T, the first full-tensor pass      */
+    TUCKER_STAGE_TTM_Y1 = 1,     /* * Y1 = T34 x2 U2^T                                         */
+    TUCKER_STAGE_GRAM_1 = 2,     /* * mode-1 Gram product (split-K partials)                   */
+    TUCKER_STAGE_OI_1 = 3,       /*   orthogonal iteration + CholeskyQR2 of mode 1             */
+    TUCKER_STAGE_TTM_Y2 = 4,     /* * Y2 = T34 x1 U1^T                                         */
+    TUCKER_STAGE_GRAM_2 = 5,     /* * mode-2 Gram product                                      */
+    TUCKER_STAGE_OI_2 = 6,       /*   orthogonal iteration + CholeskyQR2 of mode 2             */
+    TUCKER_STAGE_PASS_C1 = 7,    /* * T1 = X x1 U1^T, the second full-tensor pass              */
+    TUCKER_STAGE_TTM_C2 = 8,     /* * T12 = T1 x2 U2^T                                         */
+    TUCKER_STAGE_SMALL = 9,      /*   fibre Gram and the updates of the small modes            */
+    TUCKER_STAGE_CORE = 10,      /*   core, ||G||^2 and the per-sweep fit                      */
+    TUCKER_STAGE_REDUCE = 11,    /*   Gram split reductions                                    */
+    TUCKER_NUM_STAGES = 12
+} tucker_stage;
 
 /* Statistics of the last tucker_decompose* call on a context (host values). */
 typedef struct {
@@ -79,6 +98,8 @@ typedef struct {
     int sweeps;                  /* sweeps performed                                          */
     int chol_shifts;             /* Cholesky pivots that needed the shifted fallback          */
     size_t workspace_bytes;      /* device workspace held by the context                      */
+    double stage_ms[TUCKER_NUM_STAGES];   /* summed GPU time per stage (timing = 1)           */
+    int stage_calls[TUCKER_NUM_STAGES];   /* number of timed occurrences per stage            */
 } tucker_stats;
 
 /* Fills *o with the defaults: device 0, default stream, FP32, refine_sweeps 1,

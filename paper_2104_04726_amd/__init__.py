@@ -83,7 +83,7 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, inner_iters: int = 1, init_iters: int = 20,
                  seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
-                 refine_sweeps: int = 1):
+                 refine_sweeps: int = 1, timing: bool = False):
         import torch
         lib = _lib.lib()
         opts = _lib.Options()
@@ -99,6 +99,7 @@ class Context:
         opts.hbm_budget_bytes = int(hbm_budget_bytes)
         opts.precision = _PRECISIONS[precision]
         opts.refine_sweeps = int(refine_sweeps)
+        opts.timing = 1 if timing else 0
         self.device = int(device)
         self._h = C.c_void_p()
         _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))
@@ -234,7 +235,10 @@ class Context:
     def stats(self) -> dict:
         st = _lib.Stats()
         _check(_lib.lib().tucker_get_stats(self._h, C.byref(st)))
-        return {k: getattr(st, k) for k, _ in _lib.Stats._fields_}
+        out = {k: getattr(st, k) for k, _ in _lib.Stats._fields_ if k not in ("stage_ms", "stage_calls")}
+        out["stages"] = {name: (float(st.stage_ms[i]), int(st.stage_calls[i]))
+                         for i, name in enumerate(_lib.STAGES) if st.stage_calls[i]}
+        return out
 
 
 _default = {}

@@ -11,7 +11,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtucker_mi355x.so")
+LIB_PATH = os.environ.get("TUCKER_LIB") or os.path.join(HERE, "libtucker_mi355x.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tucker.h")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERICAL, ERR_UNSUPPORTED = range(6)
@@ -31,6 +31,7 @@ class Options(C.Structure):
         ("use_graphs", C.c_int),
         ("hbm_budget_bytes", C.c_size_t),
         ("seed", C.c_uint64),
+        ("timing", C.c_int),
     ]
 
 
@@ -43,7 +44,13 @@ class Stats(C.Structure):
         ("sweeps", C.c_int),
         ("chol_shifts", C.c_int),
         ("workspace_bytes", C.c_size_t),
+        ("stage_ms", C.c_double * 12),
+        ("stage_calls", C.c_int * 12),
     ]
+
+
+STAGES = ["pass_a", "ttm_y1", "gram_1", "oi_1", "ttm_y2", "gram_2", "oi_2", "pass_c1", "ttm_c2", "small",
+          "core", "reduce"]
 
 
 _lib = None

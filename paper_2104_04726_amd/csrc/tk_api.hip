@@ -43,6 +43,7 @@ struct tucker_ctx {
     std::string err;
     tucker_stats stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> pool;   // stage timer events (created on first use)
 };
 
 namespace {
@@ -242,6 +243,40 @@ struct Run {
     Plan p;
     hipStream_t st;
     const float* X = nullptr;
+    struct Mark {
+        int stage, b, e;
+    };
+    std::vector<Mark> marks;
+    size_t next_ev = 0;
+
+    int record() {
+        if (next_ev >= ctx->pool.size()) {
+            hipEvent_t e;
+            TK_HIP(hipEventCreate(&e));
+            ctx->pool.push_back(e);
+        }
+        TK_HIP(hipEventRecord(ctx->pool[next_ev], st));
+        return (int)next_ev++;
+    }
+};
+
+// HIP-event timer of one sweep stage, active when tucker_options.timing is set
+struct StageTimer {
+    Run& r;
+    int stage;
+    int b = -1;
+    StageTimer(Run& run, int s) : r(run), stage(s) {
+        if (r.ctx->opt.timing && stage >= 0) b = r.record();
+    }
+    ~StageTimer() {
+        if (b >= 0) {
+            try {
+                const int e = r.record();
+                r.marks.push_back({stage, b, e});
+            } catch (...) {
+            }
+        }
+    }
 };
 
 // out = in x_n U^T (contract, U: dims[n] x R)  or  in x_n U (expand, U: s x dims[n], result dim s)
@@ -305,7 +340,7 @@ void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float
 
 // Mode-n Gram of `in` (dims, order N).  LARGE: FP32 result in S32 (and FP64 in S64 when asked).
 // Small (s <= 64): FP64 result in S64.
-void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want64) {
+void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want64, int stage = -1) {
     Plan& p = r.p;
     const int64_t A = prod(dims, 0, n), s = dims[n], B = prod(dims, n + 1, N);
     if (s <= kSmallMode) {
@@ -339,7 +374,11 @@ void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want6
     if ((int64_t)nsplit * s * s > p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer too small"};
     g.c = plain(p.P, s);
     g.c_zstride = s * s;
-    TK_HIP(gemm_f32(g, oa, ob, EPI_STORE, true, r.st));
+    {
+        StageTimer t(r, stage);
+        TK_HIP(gemm_f32(g, oa, ob, EPI_STORE, true, r.st));
+    }
+    StageTimer t(r, stage >= 0 ? TUCKER_STAGE_REDUCE : -1);
     TK_HIP(gram_reduce(p.P, nsplit, s, s * s, p.S32, want64 ? p.S64 : nullptr, r.st));
 }
 
@@ -386,15 +425,26 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
     TK_HIP(gemm_f64(g, MK, MK, EPI_STORE, a32, false, r.st));
 }
 
-// U64/U32 <- orthonormal basis of span(Z) by two column-scaled CholeskyQR passes (FP64)
+// U64/U32 <- orthonormal basis of span(Z) by shifted CholeskyQR3 in FP64 (Fukaya, Kannan,
+// Nakatsukasa, Yamamoto, Yanagisawa 2020): the first pass factors the column-scaled Gram plus
+// s I with s = 11 (m n + n (n+1)) u ||W~||_2 (||W~||_2 <= n for a unit diagonal), which cannot
+// break down for any numerically full-rank Z and leaves Q1 well conditioned; two plain passes
+// then make the columns orthonormal.  Every pass maps the basis by an invertible triangular
+// factor, so the column space is that of Z.
 void orthonormalize(Run& r, const float* Z, int64_t rows, int64_t cols, double* U64, float* U32) {
     Plan& p = r.p;
+    const double u = std::ldexp(1.0, -53);
+    const double shift = 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols;
     gram_tn64(r, Z, true, rows, cols, p.W);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
     apply_tri(r, Z, true, rows, cols, p.Tm, p.Q1);
     gram_tn64(r, p.Q1, false, rows, cols, p.W);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
     apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
+    gram_tn64(r, U64, false, rows, cols, p.W);
+    TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
+    TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
     TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
 }
 
@@ -491,32 +541,48 @@ void sweep_tree(Run& r) {
     const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3];
     const int64_t R23 = R2 * R3, L = s2 * s3;
     // T34 = X x_3 U3^T x_4 U4^T (full-tensor pass, memory-bound)
-    TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.T34, r.st));
+    {
+        StageTimer t(r, TUCKER_STAGE_PASS_A);
+        TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.T34, r.st));
+    }
     // mode 1: Y0 = T34 x_2 U2^T, S0 = Y0_(1) Y0_(1)^T
     if (p.kind[0] != FIXED) {
         int64_t d[3] = {s0, s1, R23};
-        ttm(r, p.T34, d, 3, 1, p.U32[1], R1, false, p.Y0);
+        {
+            StageTimer t(r, TUCKER_STAGE_TTM_Y1);
+            ttm(r, p.T34, d, 3, 1, p.U32[1], R1, false, p.Y0);
+        }
         int64_t dy[3] = {s0, R1, R23};
-        gram(r, p.Y0, dy, 3, 0, p.kind[0] == SMALL);
+        gram(r, p.Y0, dy, 3, 0, p.kind[0] == SMALL, TUCKER_STAGE_GRAM_1);
+        StageTimer t(r, TUCKER_STAGE_OI_1);
         update_factor(r, 0, false);
     }
     // mode 2: Y1 = T34 x_1 U1^T (new U1), S1
     if (p.kind[1] != FIXED) {
         int64_t d[3] = {s0, s1, R23};
-        ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
+        {
+            StageTimer t(r, TUCKER_STAGE_TTM_Y2);
+            ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
+        }
         int64_t dy[3] = {R0, s1, R23};
-        gram(r, p.Y1, dy, 3, 1, p.kind[1] == SMALL);
+        gram(r, p.Y1, dy, 3, 1, p.kind[1] == SMALL, TUCKER_STAGE_GRAM_2);
+        StageTimer t(r, TUCKER_STAGE_OI_2);
         update_factor(r, 1, false);
     }
     // T12 = X x_1 U1^T x_2 U2^T (second full-tensor pass)
     {
         int64_t d[3] = {s0, s1, L};
-        ttm(r, r.X, d, 3, 0, p.U32[0], R0, false, p.T1);
+        {
+            StageTimer t(r, TUCKER_STAGE_PASS_C1);
+            ttm(r, r.X, d, 3, 0, p.U32[0], R0, false, p.T1);
+        }
         d[0] = R0;
+        StageTimer t(r, TUCKER_STAGE_TTM_C2);
         ttm(r, p.T1, d, 3, 1, p.U32[1], R1, false, p.T12);
     }
     // modes 3 and 4 from the fibre Gram of T12
     if (p.kind[2] != FIXED || p.kind[3] != FIXED) {
+        StageTimer t(r, TUCKER_STAGE_SMALL);
         TK_HIP(fibre_gram(p.T12, R0 * R1, (int)L, p.Fpart, kFibreGramBlocks, p.F, r.st));
         if (p.kind[2] != FIXED) {
             TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[3], (int)R3, 3, p.S64, r.st));
@@ -528,6 +594,7 @@ void sweep_tree(Run& r) {
         }
     }
     // core G = T12 x_3 U3^T x_4 U4^T
+    StageTimer t(r, TUCKER_STAGE_CORE);
     TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
 }
 
@@ -859,6 +926,7 @@ tucker_status tucker_destroy(tucker_ctx* ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return TUCKER_OK;
@@ -956,6 +1024,14 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         if (fit_history)
             for (int k = 0; k <= done; ++k) fit_history[k] = fits[k];
         if (sweeps_done) *sweeps_done = done;
+        for (int i = 0; i < TUCKER_NUM_STAGES; ++i) {
+            ctx->stats.stage_ms[i] = 0.0;
+            ctx->stats.stage_calls[i] = 0;
+        }
+        for (const auto& m : r.marks) {
+            ctx->stats.stage_ms[m.stage] += elapsed(ctx->pool[m.b], ctx->pool[m.e]);
+            ctx->stats.stage_calls[m.stage] += 1;
+        }
         ctx->stats.init_ms = elapsed(ctx->ev[0], ctx->ev[1]);
         ctx->stats.sweeps_ms = elapsed(ctx->ev[1], ctx->ev[2]);
         ctx->stats.final_fit_ms = elapsed(ctx->ev[2], ctx->ev[3]);
@@ -1083,7 +1159,7 @@ tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, doubl
         });
         TK_HIP(fill_zero(shifts, 16, ctx->stream));
         TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-        TK_HIP(chol_inv_scaled(Wc, n, true, T, (int*)cw, shifts, ctx->stream));
+        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, (int*)cw, shifts, ctx->stream));
         int sh = 0;
         TK_HIP(hipMemcpyAsync(&sh, shifts, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         TK_HIP(hipStreamSynchronize(ctx->stream));

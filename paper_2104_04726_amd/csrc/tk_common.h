@@ -116,11 +116,11 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // ---------------------------------------------------------------------------------------
 // Dense linear algebra (tk_linalg.hip)
 // ---------------------------------------------------------------------------------------
-// In place on W (n x n fp64, lower triangle read): column-scaled Cholesky W~ = D^-1 W D^-1 =
-// L L^T by a tiled task graph, then T = L^-1 D^-1 (lower triangular) written to Tout.
+// In place on W (n x n fp64, lower triangle read): column-scaled Cholesky W~ + shift I = L L^T
+// (W~ = D^-1 W D^-1) by a tiled task graph, then T = L^-1 D^-1 (lower triangular) to Tout.
 // counters: int workspace of chol_counter_ints(n) entries (zeroed by the call).
 // shifts: int counter incremented for every pivot that needed the shifted fallback.
-hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double* Tout, int* counters,
+hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
                            int* shifts, hipStream_t s);
 int64_t chol_counter_ints(int64_t n);
 

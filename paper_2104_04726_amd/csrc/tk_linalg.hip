@@ -25,6 +25,7 @@ struct CholArgs {
     double* W;
     int64_t n;
     int T;
+    double shift;          // added to the diagonal of the scaled matrix
     const double* dsc;     // 1/sqrt(W_ii) (or 1)
     double* Tout;
     int* ticket;
@@ -61,9 +62,9 @@ __device__ void release_flag(int* f) {
 }
 
 // tile (ti,tj) of an n x n row-major matrix -> LDS t; out-of-range -> 0 (or 1 on the diagonal
-// when pad_diag), optionally scaled by dsc[r] dsc[c]
+// when pad_diag), optionally scaled by dsc[r] dsc[c] and shifted on the diagonal
 __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dsc,
-                          bool pad_diag) {
+                          bool pad_diag, double shift = 0.0) {
     for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
         const int r = e / TB, c = e % TB;
         const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
@@ -71,6 +72,7 @@ __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t,
         if (gr < n && gc < n) {
             v = M[gr * n + gc];
             if (dsc) v *= dsc[gr] * dsc[gc];
+            if (gr == gc) v += shift;
         } else {
             v = (pad_diag && gr == gc) ? 1.0 : 0.0;
         }
@@ -198,7 +200,8 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             ++j;
         }
         const int i = j + rem;
-        load_tile(a.W, a.n, i, j, At, a.dsc, i == j);
+        load_tile(a.W, a.n, i, j, At, a.dsc, i == j, i == j ? a.shift : 0.0);
+        __syncthreads();   // the whole tile is in LDS before wave 0 may factor it (j == 0)
         for (int k = 0; k < j; ++k) {
             wait_flags(fL(i, k), fL(j, k), a.err);
             load_tile(a.W, a.n, i, k, Bt, nullptr, false);
@@ -248,6 +251,11 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
         store_tile(a.Tout, a.n, i, j, Bt);
         release_flag(fI(i, j));
     }
+}
+
+// a timed-out wait of the task graph is reported through the shift counter (+1e6)
+__global__ void chol_report(const int* err, int* shifts) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *err) atomicAdd(shifts, 1000000);
 }
 
 // T <- lower(T) * D^-1 (column scaling), upper triangle zeroed
@@ -382,8 +390,8 @@ int64_t chol_counter_ints(int64_t n) {
     return 2 + 2 * T * T;
 }
 
-hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double* Tout, int* counters, int* shifts,
-                           hipStream_t s) {
+hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
+                           int* shifts, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int T = (int)((n + TB - 1) / TB);
     // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); dsc stored after Tout?  no:
@@ -393,8 +401,10 @@ hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double* Tout, int* 
     double* dsc = (double*)(((uintptr_t)(counters + chol_counter_ints(n)) + 15) & ~(uintptr_t)15);
     hipLaunchKernelGGL(chol_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, scale, dsc, shifts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    CholArgs a{W, n, T, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1};
+    CholArgs a{W, n, T, shift, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1};
     hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T)), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(chol_report, dim3(1), dim3(64), 0, s, counters + 1, shifts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t total = n * n;
     hipLaunchKernelGGL(chol_epilogue, dim3((unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096)),

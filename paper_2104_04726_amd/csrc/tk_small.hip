@@ -432,13 +432,14 @@ __global__ void fit_norms_kernel(const double* nx2, const double* ng2, double* f
             return;
         }
         const double d = a - *ng2;
-        *fit = 1.0 - sqrt(d > 0.0 ? d : 0.0) / sqrt(a);
+        *fit = 1.0 - sqrt(d < 0.0 ? 0.0 : d) / sqrt(a);     // a NaN difference stays NaN
     }
 }
 __global__ void fit_resid_kernel(const double* nx2, const double* r2, double* fit) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const double a = *nx2;
-        *fit = (a > 0.0) ? 1.0 - sqrt(*r2 > 0.0 ? *r2 : 0.0) / sqrt(a) : 1.0;
+        const double r = *r2;
+        *fit = (a > 0.0) ? 1.0 - sqrt(r < 0.0 ? 0.0 : r) / sqrt(a) : 1.0;   // NaN propagates
     }
 }
 
