@@ -101,11 +101,10 @@ struct Plan {
     float *Ya = nullptr, *Yb = nullptr;
     float* G = nullptr;
     // Gram / OI
-    float* S32 = nullptr;
     double* S64 = nullptr;
-    float* P = nullptr;
+    double* P = nullptr;
     int64_t P_elems = 0;
-    float* Z = nullptr;
+    double* Z = nullptr;
     double* Q1 = nullptr;
     double* W = nullptr;
     double* Wpart = nullptr;
@@ -168,7 +167,7 @@ int64_t chain_max(const Plan& p) {
 constexpr int kGramTargetBlocks = 1024;
 
 int gram_splits(int64_t s, int64_t K) {
-    const int64_t t = (s + 127) / 128;
+    const int64_t t = (s + 63) / 64;       // 64 x 64 FP64 MFMA tiles
     const int64_t tiles = t * (t + 1) / 2;
     int64_t sp = (kGramTargetBlocks + tiles - 1) / tiles;
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
@@ -212,12 +211,11 @@ void build_plan(Plan& p, Arena& a) {
             maxsmall = std::max(maxsmall, p.s[n]);
         }
     }
-    p.S32 = a.take<float>(std::max<int64_t>(maxs * maxs, 1));
     p.S64 = a.take<double>(std::max<int64_t>(std::max(maxs, maxsmall) * std::max(maxs, maxsmall), 64 * 64));
-    p.P = a.take<float>(pmax);
+    p.P = a.take<double>(pmax);
     p.P_elems = pmax;
     const int64_t sR = max_large_sR(p), Rm = max_large_R(p);
-    p.Z = a.take<float>(sR);
+    p.Z = a.take<double>(sR);
     p.Q1 = a.take<double>(sR);
     p.W = a.take<double>(Rm * Rm);
     p.Wpart_elems = 16 * Rm * Rm;
@@ -338,12 +336,15 @@ void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float
     }
 }
 
-// Mode-n Gram of `in` (dims, order N).  LARGE: FP32 result in S32 (and FP64 in S64 when asked).
-// Small (s <= 64): FP64 result in S64.
-void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want64, int stage = -1) {
+// Mode-n Gram of `in` (dims, order N) into S64 (FP64, s x s, symmetric).  Large modes use the
+// FP64 MFMA kernel on the FP32 data (every product exact, FP64 accumulation; a FP32-accumulated
+// Gram loses the directions next to the rank boundary of strongly decaying spectra), split over K
+// with FP64 partials summed in a fixed order; small modes use the vector kernel.
+void gram(Run& r, const float* in, const int64_t* dims, int N, int n, int stage = -1) {
     Plan& p = r.p;
     const int64_t A = prod(dims, 0, n), s = dims[n], B = prod(dims, n + 1, N);
     if (s <= kSmallMode) {
+        StageTimer t(r, stage);
         TK_HIP(small_gram(in, A, s, B, p.Fpart, kFibreGramBlocks / 8, p.S64, r.st));
         return;
     }
@@ -368,7 +369,7 @@ void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want6
     }
     const int splits = gram_splits(s, g.K);
     int64_t ks = (g.K + splits - 1) / splits;
-    ks = (ks + 31) / 32 * 32;
+    ks = (ks + 15) / 16 * 16;
     g.k_split = ks;
     const int nsplit = (int)((g.K + ks - 1) / ks);
     if ((int64_t)nsplit * s * s > p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer too small"};
@@ -376,10 +377,10 @@ void gram(Run& r, const float* in, const int64_t* dims, int N, int n, bool want6
     g.c_zstride = s * s;
     {
         StageTimer t(r, stage);
-        TK_HIP(gemm_f32(g, oa, ob, EPI_STORE, true, r.st));
+        TK_HIP(gemm_f64(g, oa, ob, EPI_STORE, true, true, r.st));
     }
     StageTimer t(r, stage >= 0 ? TUCKER_STAGE_REDUCE : -1);
-    TK_HIP(gram_reduce(p.P, nsplit, s, s * s, p.S32, want64 ? p.S64 : nullptr, r.st));
+    TK_HIP(gram_reduce64(p.P, nsplit, s, s * s, p.S64, r.st));
 }
 
 // W = A^T A (FP64) for A (rows x cols), A float or double, split over rows
@@ -425,31 +426,39 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
     TK_HIP(gemm_f64(g, MK, MK, EPI_STORE, a32, false, r.st));
 }
 
-// U64/U32 <- orthonormal basis of span(Z) by shifted CholeskyQR3 in FP64 (Fukaya, Kannan,
-// Nakatsukasa, Yamamoto, Yanagisawa 2020): the first pass factors the column-scaled Gram plus
-// s I with s = 11 (m n + n (n+1)) u ||W~||_2 (||W~||_2 <= n for a unit diagonal), which cannot
-// break down for any numerically full-rank Z and leaves Q1 well conditioned; two plain passes
-// then make the columns orthonormal.  Every pass maps the basis by an invertible triangular
-// factor, so the column space is that of Z.
-void orthonormalize(Run& r, const float* Z, int64_t rows, int64_t cols, double* U64, float* U32) {
+// U64/U32 <- orthonormal basis of span(Z) by CholeskyQR in FP64 with column scaling.
+// cold: shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): the first pass
+// factors the scaled Gram plus s I, s = 11 (m n + n (n+1)) u ||W~||_2 with ||W~||_2 <= n (unit
+// diagonal), which cannot break down for a numerically full-rank Z and leaves Q1 well conditioned;
+// two plain passes follow.  warm (Z = S U with U near the invariant subspace, cond(Z) well below
+// u^-1/2): CholeskyQR2.  Each pass maps the basis by an invertible triangular factor, so the column
+// space is that of Z.
+void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
+                    bool cold) {
     Plan& p = r.p;
     const double u = std::ldexp(1.0, -53);
-    const double shift = 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols;
-    gram_tn64(r, Z, true, rows, cols, p.W);
+    const double shift = cold ? 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols : 0.0;
+    // pass 1: Z -> Q1
+    gram_tn64(r, Z, z32, rows, cols, p.W);
     TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
-    apply_tri(r, Z, true, rows, cols, p.Tm, p.Q1);
+    apply_tri(r, Z, z32, rows, cols, p.Tm, p.Q1);
+    // pass 2: Q1 -> U64 (cold: -> Q1 again through U64, pass 3)
     gram_tn64(r, p.Q1, false, rows, cols, p.W);
     TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
-    apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
-    gram_tn64(r, U64, false, rows, cols, p.W);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
-    apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
-    TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
+    if (!cold) {
+        apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
+    } else {
+        apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
+        gram_tn64(r, U64, false, rows, cols, p.W);
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+        apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
+        TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
+    }
     TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
 }
 
-// q steps of orthogonal iteration on S32 (s x s), warm start from U32
-void orth_iter(Run& r, int n, int q) {
+// q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR
+void orth_iter(Run& r, int n, int q, bool cold) {
     Plan& p = r.p;
     const int64_t s = p.s[n], R = p.R[n];
     for (int it = 0; it < q; ++it) {
@@ -458,15 +467,15 @@ void orth_iter(Run& r, int n, int q) {
         g.M = s;
         g.N = R;
         g.K = s;
-        g.a = plain(p.S32, s);      // A(m, k) = S[k][m] (symmetric)
-        g.b = plain(p.U32[n], R);
+        g.a = plain(p.S64, s);      // A(m, k) = S[k][m] (symmetric)
+        g.b = plain(p.U64[n], R);
         g.c = plain(p.Z, R);
-        TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
-        orthonormalize(r, p.Z, s, R, p.U64[n], p.U32[n]);
+        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+        orthonormalize(r, p.Z, false, s, R, p.U64[n], p.U32[n], cold && it < 2);
     }
 }
 
-// factor update of mode n from the Gram already in S32 / S64
+// factor update of mode n from the Gram in S64
 void update_factor(Run& r, int n, bool cold) {
     Plan& p = r.p;
     if (p.kind[n] == FIXED) return;
@@ -477,9 +486,10 @@ void update_factor(Run& r, int n, bool cold) {
     if (cold) {
         TK_HIP(fill_random(p.U32[n], p.s[n] * p.R[n], r.ctx->opt.seed * 0x100000001b3ull + (uint64_t)n * 0x9e3779b9ull,
                            r.st));
-        orth_iter(r, n, std::max(1, r.ctx->opt.init_iters));
+        TK_HIP(f32_to_f64(p.U32[n], p.U64[n], p.s[n] * p.R[n], r.st));
+        orth_iter(r, n, std::max(1, r.ctx->opt.init_iters), true);
     } else {
-        orth_iter(r, n, std::max(1, r.ctx->opt.inner_iters));
+        orth_iter(r, n, std::max(1, r.ctx->opt.inner_iters), false);
     }
 }
 
@@ -529,7 +539,7 @@ void thosvd(Run& r) {
             identity_factor(r, n);
             continue;
         }
-        gram(r, r.X, p.s, p.N, n, false);
+        gram(r, r.X, p.s, p.N, n);
         update_factor(r, n, true);
     }
 }
@@ -553,7 +563,7 @@ void sweep_tree(Run& r) {
             ttm(r, p.T34, d, 3, 1, p.U32[1], R1, false, p.Y0);
         }
         int64_t dy[3] = {s0, R1, R23};
-        gram(r, p.Y0, dy, 3, 0, p.kind[0] == SMALL, TUCKER_STAGE_GRAM_1);
+        gram(r, p.Y0, dy, 3, 0, TUCKER_STAGE_GRAM_1);
         StageTimer t(r, TUCKER_STAGE_OI_1);
         update_factor(r, 0, false);
     }
@@ -565,7 +575,7 @@ void sweep_tree(Run& r) {
             ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
         }
         int64_t dy[3] = {R0, s1, R23};
-        gram(r, p.Y1, dy, 3, 1, p.kind[1] == SMALL, TUCKER_STAGE_GRAM_2);
+        gram(r, p.Y1, dy, 3, 1, TUCKER_STAGE_GRAM_2);
         StageTimer t(r, TUCKER_STAGE_OI_2);
         update_factor(r, 1, false);
     }
@@ -616,7 +626,7 @@ void sweep_generic(Run& r) {
             w ^= 1;
         }
         if (p.kind[n] != FIXED) {
-            gram(r, cur, d, N, n, p.kind[n] == SMALL);
+            gram(r, cur, d, N, n);
             update_factor(r, n, false);
         }
     }
@@ -1099,13 +1109,12 @@ tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int6
         const int64_t K = prod(dims, 0, ndim) / sdim;
         with_scratch(ctx, [&](Arena& a) {
             p.Fpart = a.take<double>(64 * 64 * 64);
-            p.S64 = a.take<double>(sdim <= kSmallMode ? sdim * sdim : 1);
+            p.S64 = a.take<double>(sdim * sdim);
             p.P_elems = (int64_t)gram_splits(sdim, K) * sdim * sdim;
-            p.P = a.take<float>(sdim > kSmallMode ? p.P_elems : 1);
+            p.P = a.take<double>(sdim > kSmallMode ? p.P_elems : 1);
         });
-        p.S32 = out;
-        gram(r, in, dims, ndim, mode, false);
-        if (sdim <= kSmallMode) TK_HIP(f64_to_f32(p.S64, out, sdim * sdim, r.st));
+        gram(r, in, dims, ndim, mode);
+        TK_HIP(f64_to_f32(p.S64, out, sdim * sdim, r.st));
     });
 }
 
@@ -1127,7 +1136,7 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
             U64 = a.take<double>(rows * cols);
         });
         TK_HIP(fill_zero(p.shifts, 16, r.st));
-        orthonormalize(r, Z, rows, cols, U64, Q);
+        orthonormalize(r, Z, true, rows, cols, U64, Q, true);
     });
 }
 

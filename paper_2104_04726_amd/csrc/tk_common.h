@@ -102,6 +102,8 @@ hipError_t small_gram(const float* in, int64_t A, int64_t sdim, int64_t B, doubl
 hipError_t gram_reduce(const float* P, int nsplit, int64_t n, int64_t zstride, float* S32,
                        double* S64, hipStream_t s);
 
+hipError_t gram_reduce64(const double* P, int nsplit, int64_t n, int64_t zstride, double* S64, hipStream_t s);
+
 hipError_t f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
 hipError_t fill_identity_f32(float* out, int64_t rows, int64_t cols, hipStream_t s);

@@ -7,8 +7,8 @@
 //   Each workgroup claims the next task with an atomic ticket, so every task it waits for was
 //   claimed earlier by a running workgroup: the graph cannot deadlock whatever the residency.
 //   Waits are bounded spins; a timeout raises an error flag instead of hanging.
-//   Producer: stores, agent-scope fence, barrier, flag store-release.
-//   Consumer: flag load-acquire, barrier, agent-scope fence, loads.
+//   Producer: coherent stores, wait for their completion, barrier, coherent flag store.
+//   Consumer: coherent flag load, barrier, coherent loads.
 //
 // jacobi_eig: cyclic two-sided Jacobi (Golub & Van Loan, Alg. 8.4.3, with the parallel
 //   round-robin ordering) on a symmetric matrix of order <= 64 held in LDS.
@@ -35,30 +35,45 @@ struct CholArgs {
     int* err;
 };
 
-__device__ __forceinline__ int ld_acq(int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Shared tiles and flags are accessed with agent-scope relaxed atomics, which are coherent across
+// the XCDs without whole-L2 writeback/invalidate.  A producer waits for its stores to complete
+// (vmcnt 0) before the workgroup barrier that precedes the flag store; a consumer issues its tile
+// loads only after observing the flag.
+__device__ __forceinline__ int ld_flag(int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_flag(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ void wait_flags(int* f1, int* f2, int* err) {
     if (threadIdx.x == 0) {
         long long it = 0;
-        while ((ld_acq(f1) == 0 || (f2 && ld_acq(f2) == 0)) && it < kMaxSpin) {
+        while ((ld_flag(f1) == 0 || (f2 && ld_flag(f2) == 0)) && it < kMaxSpin) {
             __builtin_amdgcn_s_sleep(1);
             ++it;
         }
-        if (it >= kMaxSpin) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (it >= kMaxSpin) st_flag(err, 1);
     }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
-    __threadfence();
 }
 
 __device__ void release_flag(int* f) {
-    __threadfence();
+    stores_done();
     __syncthreads();
-    if (threadIdx.x == 0) st_rel(f, 1);
+    if (threadIdx.x == 0) st_flag(f, 1);
 }
 
 // tile (ti,tj) of an n x n row-major matrix -> LDS t; out-of-range -> 0 (or 1 on the diagonal
@@ -70,7 +85,7 @@ __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t,
         const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
         double v;
         if (gr < n && gc < n) {
-            v = M[gr * n + gc];
+            v = ld_coh(&M[gr * n + gc]);
             if (dsc) v *= dsc[gr] * dsc[gc];
             if (gr == gc) v += shift;
         } else {
@@ -84,7 +99,7 @@ __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t
     for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
         const int r = e / TB, c = e % TB;
         const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
-        if (gr < n && gc < n) M[gr * n + gc] = t[r * TS + c];
+        if (gr < n && gc < n) st_coh(&M[gr * n + gc], t[r * TS + c]);
     }
 }
 
@@ -214,11 +229,11 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             tile_trtri(At, Bt);
             store_tile(a.W, a.n, j, j, At);
             store_tile(a.Tout, a.n, j, j, Bt);
-            __threadfence();
+            stores_done();
             __syncthreads();
             if (threadIdx.x == 0) {
-                st_rel(fL(j, j), 1);
-                st_rel(fI(j, j), 1);
+                st_flag(fL(j, j), 1);
+                st_flag(fI(j, j), 1);
             }
         } else {
             wait_flags(fL(j, j), nullptr, a.err);

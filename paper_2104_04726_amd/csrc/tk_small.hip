@@ -263,9 +263,9 @@ __global__ __launch_bounds__(256) void fibre_gram_kernel(const float* __restrict
         __syncthreads();
         for (int u = 0; u < 9; ++u) {
             if (pi[u] < 0) continue;
-            float a = 0.f;
-            for (int f = 0; f < nf; ++f) a = fmaf(xs[f * 65 + pi[u]], xs[f * 65 + pj[u]], a);
-            accd[u] += (double)a;      // FP64 across chunks of 64 fibres
+            double a = 0.0;
+            for (int f = 0; f < nf; ++f) a = fma((double)xs[f * 65 + pi[u]], (double)xs[f * 65 + pj[u]], a);
+            accd[u] += a;              // products of FP32 values are exact in FP64
         }
     }
     double* dst = partial + (int64_t)blockIdx.x * L * L;
@@ -365,9 +365,9 @@ __global__ __launch_bounds__(256) void small_gram_kernel(const float* __restrict
         __syncthreads();
         for (int u = 0; u < 9; ++u) {
             if (pi[u] < 0) continue;
-            float acc = 0.f;
-            for (int cc = 0; cc < nc; ++cc) acc = fmaf(cs[cc * 65 + pi[u]], cs[cc * 65 + pj[u]], acc);
-            accd[u] += (double)acc;
+            double acc = 0.0;
+            for (int cc = 0; cc < nc; ++cc) acc = fma((double)cs[cc * 65 + pi[u]], (double)cs[cc * 65 + pj[u]], acc);
+            accd[u] += acc;
         }
     }
     double* dst = partial + (int64_t)blockIdx.x * s * s;
@@ -389,6 +389,20 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const float* __restric
         for (int z = 0; z < nsplit; ++z) s += (double)P[z * zstride + src];
         if (S32) S32[e] = (float)s;
         if (S64) S64[e] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce64_kernel(const double* __restrict__ P, int nsplit,
+                                                            int64_t n, int64_t zstride,
+                                                            double* __restrict__ S64) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
+        double s = 0.0;
+        for (int z = 0; z < nsplit; ++z) s += P[z * zstride + src];
+        S64[e] = s;
     }
 }
 
@@ -548,6 +562,12 @@ hipError_t gram_reduce(const float* P, int nsplit, int64_t n, int64_t zstride, f
                        hipStream_t s) {
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(n * n, 4096)), dim3(256), 0, s, P, nsplit, n, zstride,
                        S32, S64);
+    return hipGetLastError();
+}
+
+hipError_t gram_reduce64(const double* P, int nsplit, int64_t n, int64_t zstride, double* S64, hipStream_t s) {
+    hipLaunchKernelGGL(gram_reduce64_kernel, dim3(grid_for(n * n, 4096)), dim3(256), 0, s, P, nsplit, n, zstride,
+                       S64);
     return hipGetLastError();
 }
 
