@@ -2,7 +2,7 @@
 //
 // chol_inv_scaled: W~ = D^-1 W D^-1 (D = sqrt(diag W)) is factored W~ = L L^T and T = L^-1 D^-1 is
 //   produced, so that Q = Z T^T has orthonormal columns when W = Z^T Z (one CholeskyQR pass).
-//   The n x n problem is split into 32 x 32 tiles and run as one launch of a tiled task graph:
+//   The n x n problem is split into 64 x 64 tiles and run as one launch of a tiled task graph:
 //   factor tasks (i,j), i >= j, in column-major order, then inverse tasks (i,j), i > j.
 //   Each workgroup claims the next task with an atomic ticket, so every task it waits for was
 //   claimed earlier by a running workgroup: the graph cannot deadlock whatever the residency.
@@ -17,8 +17,11 @@
 namespace tk {
 namespace {
 
-constexpr int TB = 32;
-constexpr int TS = 33;                      // padded LDS row stride
+#ifndef TK_CHOL_TB
+#define TK_CHOL_TB 64
+#endif
+constexpr int TB = TK_CHOL_TB;
+constexpr int TS = TB + 1;                  // padded LDS row stride
 constexpr long long kMaxSpin = 1ll << 24;   // bounded waits (x ~64 cycles of sleep each)
 
 struct CholArgs {
@@ -103,26 +106,38 @@ __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t
     }
 }
 
-// C = beta*C + alpha * A * op(B), op(B) = B^T when transB.  256 threads, 4 outputs each.
+// C = beta*C + alpha * A * op(B), op(B) = B^T when transB.  256 threads; thread t owns the 4x4
+// block at rows 4 (t / 16), columns 4 (t % 16) (TB = 64).
 __device__ void tile_gemm(double* C, const double* A, const double* B, bool transB, double alpha,
                           double beta) {
-    const int r = threadIdx.x >> 3;
-    const int c0 = (threadIdx.x & 7) * 4;
-    double acc[4] = {0, 0, 0, 0};
-    for (int k = 0; k < TB; ++k) {
-        const double a = A[r * TS + k];
+    static_assert(TB == 64, "tile_gemm assumes 64 x 64 tiles and 256 threads");
+    const int r0 = (threadIdx.x >> 4) * 4;
+    const int c0 = (threadIdx.x & 15) * 4;
+    double acc[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double b = transB ? B[(c0 + u) * TS + k] : B[k * TS + c0 + u];
-            acc[u] = fma(a, b, acc[u]);
-        }
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < TB; ++k) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = A[(r0 + a) * TS + k];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = transB ? B[(c0 + b) * TS + k] : B[k * TS + c0 + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();   // C may alias A or B
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        double* d = &C[r * TS + c0 + u];
-        *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[u];
-    }
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            double* d = &C[(r0 + a) * TS + c0 + b];
+            *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[a][b];
+        }
     __syncthreads();
 }
 
@@ -132,52 +147,172 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// In-LDS Cholesky of a 32x32 tile (lower), by wave 0; lane i owns row i.  Pivots that are not
-// safely positive are replaced (shifted fallback) and counted.  Upper triangle is zeroed.
-__device__ void tile_potrf(double* A, int* shifts) {
-    if (threadIdx.x < 64) {
-        const int i = threadIdx.x;
-        for (int k = 0; k < TB; ++k) {
-            if (i == k) {
-                double d = A[k * TS + k];
-                if (!(d > 1e-13)) {
-                    d = 1e-13;
-                    atomicAdd(shifts, 1);
-                }
-                A[k * TS + k] = sqrt(d);
-            }
-            wave_sync();
-            const double piv = A[k * TS + k];
-            if (i > k && i < TB) A[i * TS + k] /= piv;
-            wave_sync();
-            if (i > k && i < TB) {
-                const double lik = A[i * TS + k];
-                for (int j = k + 1; j <= i; ++j) A[i * TS + j] -= lik * A[j * TS + k];
-            }
-            wave_sync();
+// ---- 64 x 64 tile factorisation and inversion, blocked by 16: the sequential parts are 16 x 16
+// problems solved inside one wave's registers (row r in lane r, column entries broadcast with
+// readlane, no barriers); the rest is parallel over the workgroup with a barrier per phase.
+constexpr int SB = 16;   // inner block
+static_assert(TB == 64, "blocked tile kernels assume 64 x 64 tiles");
+
+__device__ __forceinline__ double safe_pivot(double d) { return (d > 1e-13) ? d : 1e-13; }
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One wave: Cholesky of the 16 x 16 diagonal block at (o, o) of A (LDS, row stride TS), in place
+// (lower L, upper zeroed), and its inverse into Y (LDS 16 x 16, row stride SB).  L D L^T form: the
+// pivots are divided out once per column and the square roots applied at the end.
+__device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
+    const int r = threadIdx.x & 63;
+    const bool act = r < SB;
+    double a[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) a[j] = act ? A[(o + r) * TS + o + j] : 0.0;
+    double dk[SB];
+#pragma unroll
+    for (int k = 0; k < SB; ++k) {
+        const double d = readlane_f64(a[k], k);          // current pivot
+        dk[k] = d;
+        const double inv = 1.0 / safe_pivot(d);
+        const double c = a[k];                           // unscaled column entry of this row
+#pragma unroll
+        for (int j = k + 1; j < SB; ++j) {
+            const double cj = readlane_f64(c, j);
+            if (r >= j) a[j] -= c * cj * inv;
         }
-        if (i < TB)
-            for (int j = i + 1; j < TB; ++j) A[i * TS + j] = 0.0;
+    }
+    if (r == 0) {
+#pragma unroll
+        for (int k = 0; k < SB; ++k)
+            if (!(dk[k] > 1e-13)) atomicAdd(shifts, 1);
+    }
+    double sq[SB];
+#pragma unroll
+    for (int k = 0; k < SB; ++k) sq[k] = sqrt(safe_pivot(dk[k]));
+    // L_rj = a_rj / sqrt(d_j) (j < r), L_rr = sqrt(d_r)
+#pragma unroll
+    for (int j = 0; j < SB; ++j) a[j] = (j < r) ? a[j] / sq[j] : ((j == r) ? sq[j] : 0.0);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < SB; ++j) A[(o + r) * TS + o + j] = a[j];
+    }
+    // inverse: lane c computes column c of L^-1 by forward substitution (rows broadcast by readlane)
+    double x[SB];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+        double acc = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= readlane_f64(a[k], i) * x[k];
+        x[i] = (i < r) ? 0.0 : acc / sq[i];
+    }
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < SB; ++i) Y[i * SB + r] = x[i];
+    }
+}
+
+// In-LDS Cholesky of the 64 x 64 tile A (lower; upper zeroed).  Right-looking over the four 16-wide
+// block columns: wave factor + inverse of the diagonal block, TRSM of the block column below,
+// SYRK update of the trailing lower triangle.
+__device__ void tile_potrf(double* A, int* shifts) {
+    __shared__ double Y[SB * SB];
+    const int tid = threadIdx.x;
+    for (int b = 0; b < TB / SB; ++b) {
+        const int o = b * SB;
+        if (tid < 64) wave_potrf16(A, o, Y, shifts);
+        __syncthreads();
+        const int rows = TB - o - SB;
+        if (rows > 0) {
+            // L_ic = sum_{k <= c} A_ik Y_ck for i >= o + 16, c in the block (Y = L_bb^-1)
+            double vals[3];
+            int cnt = 0;
+            for (int e = tid; e < rows * SB; e += blockDim.x) {
+                const int i = o + SB + e / SB, c = e % SB;
+                double acc = 0.0;
+                for (int k = 0; k <= c; ++k) acc += A[i * TS + o + k] * Y[c * SB + k];
+                vals[cnt++] = acc;
+            }
+            __syncthreads();
+            cnt = 0;
+            for (int e = tid; e < rows * SB; e += blockDim.x) {
+                const int i = o + SB + e / SB, c = e % SB;
+                A[i * TS + o + c] = vals[cnt++];
+            }
+            __syncthreads();
+            // trailing lower triangle: A_ij -= sum_c L_ic L_jc, o+16 <= j <= i
+            for (int e = tid; e < rows * rows; e += blockDim.x) {
+                const int ii = e / rows, jj = e % rows;
+                if (jj > ii) continue;
+                const int i = o + SB + ii, j = o + SB + jj;
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < SB; ++c) acc += A[i * TS + o + c] * A[j * TS + o + c];
+                A[i * TS + j] -= acc;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < TB * TB; e += blockDim.x) {
+        const int i = e / TB, j = e % TB;
+        if (j > i) A[i * TS + j] = 0.0;
     }
     __syncthreads();
 }
 
-// Inverse of a lower-triangular 32x32 tile L (LDS) into X (LDS); lane c computes column c.
+// Inverse of the lower-triangular 64 x 64 tile L (LDS) into X (LDS): the four diagonal 16 x 16
+// inverses by four waves in parallel, then block forward substitution over the block rows:
+// X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
+__device__ void wave_trtri16(const double* L, int o, double* X) {
+    const int c = threadIdx.x & 63;
+    double x[SB];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+        double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= L[(o + i) * TS + o + k] * x[k];
+        x[i] = (i < c) ? 0.0 : acc / L[(o + i) * TS + o + i];
+    }
+    if (c < SB) {
+#pragma unroll
+        for (int i = 0; i < SB; ++i) X[(o + i) * TS + o + c] = x[i];
+    }
+}
+
 __device__ void tile_trtri(const double* L, double* X) {
-    if (threadIdx.x < TB) {
-        const int c = threadIdx.x;
-        double x[TB];
-#pragma unroll
-        for (int i = 0; i < TB; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) s -= L[i * TS + k] * x[k];
-            x[i] = (i < c) ? 0.0 : s / L[i * TS + i];
-        }
-#pragma unroll
-        for (int i = 0; i < TB; ++i) X[i * TS + c] = x[i];
+    __shared__ double Tm[3 * SB * SB];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < TB * TB; e += blockDim.x) {
+        const int i = e / TB, j = e % TB;
+        X[i * TS + j] = 0.0;
     }
     __syncthreads();
+    wave_trtri16(L, (tid >> 6) * SB, X);     // wave w inverts diagonal block w
+    __syncthreads();
+    for (int bi = 1; bi < TB / SB; ++bi) {
+        // T_j = sum_{k=j}^{bi-1} L_{bi,k} X_{k,j}   for j < bi
+        for (int e = tid; e < bi * SB * SB; e += blockDim.x) {
+            const int bj = e / (SB * SB), rr = (e / SB) % SB, cc = e % SB;
+            double acc = 0.0;
+            for (int bk = bj; bk < bi; ++bk)
+#pragma unroll
+                for (int k = 0; k < SB; ++k)
+                    acc += L[(bi * SB + rr) * TS + bk * SB + k] * X[(bk * SB + k) * TS + bj * SB + cc];
+            Tm[e] = acc;
+        }
+        __syncthreads();
+        // X_{bi,j} = -X_{bi,bi} T_j
+        for (int e = tid; e < bi * SB * SB; e += blockDim.x) {
+            const int bj = e / (SB * SB), rr = (e / SB) % SB, cc = e % SB;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < SB; ++k) acc += X[(bi * SB + rr) * TS + bi * SB + k] * Tm[bj * SB * SB + k * SB + cc];
+            X[(bi * SB + rr) * TS + bj * SB + cc] = -acc;
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(256) void chol_prologue(const double* W, int64_t n, bool scale, double* dsc,

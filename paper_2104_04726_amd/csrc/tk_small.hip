@@ -226,6 +226,148 @@ __global__ __launch_bounds__(256) void pair_ttm_kernel(const float* __restrict__
     }
 }
 
+// ---------------------------------------------------------------- specialised two-mode pass
+// Same product as pair_ttm_kernel for a compile-time fibre shape: factors live in registers (U3)
+// and LDS (U4 rows read as 16-byte vectors), all index arithmetic is by constants, and the next
+// chunk's 16-byte coalesced loads are issued into registers before the current chunk is mapped,
+// so HBM reads overlap the arithmetic.
+template <int P, int Q, int R3, int R4, bool EXPAND>
+__global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ in, int64_t A,
+                                                      const float* __restrict__ U3,
+                                                      const float* __restrict__ U4,
+                                                      float* __restrict__ out) {
+    constexpr int LIN = EXPAND ? R3 * R4 : P * Q;
+    constexpr int LOUT = EXPAND ? P * Q : R3 * R4;
+    constexpr int SIN = LIN | 1, SOUT = LOUT | 1;
+    constexpr int FPB = 256;
+    constexpr int NV_IN = (FPB * LIN) / 4;          // float4 per full chunk (LIN*256 divisible by 4)
+    constexpr int NV_OUT = (FPB * LOUT) / 4;
+    constexpr int VPT_IN = (NV_IN + 255) / 256;     // float4 loads per thread
+    __shared__ float fin[FPB * SIN];
+    __shared__ float fout[FPB * SOUT];
+    __shared__ float u4s[Q * R4];
+    for (int i = threadIdx.x; i < Q * R4; i += 256) u4s[i] = U4[i];
+    float u3[P * R3];
+#pragma unroll
+    for (int i = 0; i < P * R3; ++i) u3[i] = U3[i];
+
+    const int64_t nchunks = (A + FPB - 1) / FPB;
+    const int64_t full_chunks = A / FPB;
+    float4 pre[VPT_IN];
+    auto prefetch = [&](int64_t ch) {
+        if (ch < full_chunks) {
+            const float4* src = (const float4*)(in + ch * FPB * LIN);
+#pragma unroll
+            for (int u = 0; u < VPT_IN; ++u) {
+                const int i = threadIdx.x + 256 * u;
+                if (i < NV_IN) pre[u] = src[i];
+            }
+        }
+    };
+    int64_t ch = blockIdx.x;
+    prefetch(ch);
+    for (; ch < nchunks; ch += gridDim.x) {
+        const int64_t f0 = ch * FPB;
+        const int nf = (int)((A - f0) < FPB ? (A - f0) : FPB);
+        __syncthreads();
+        if (ch < full_chunks) {
+#pragma unroll
+            for (int u = 0; u < VPT_IN; ++u) {
+                const int i = threadIdx.x + 256 * u;
+                if (i < NV_IN) {
+                    const float vv[4] = {pre[u].x, pre[u].y, pre[u].z, pre[u].w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int g = 4 * i + j;
+                        fin[(g / LIN) * SIN + (g % LIN)] = vv[j];
+                    }
+                }
+            }
+        } else {
+            const float* src = in + f0 * LIN;
+            for (int g = threadIdx.x; g < nf * LIN; g += 256) fin[(g / LIN) * SIN + (g % LIN)] = src[g];
+        }
+        __syncthreads();
+        prefetch(ch + gridDim.x);
+        const int f = threadIdx.x;
+        if (f < nf) {
+            const float* x = fin + f * SIN;
+            float* y = fout + f * SOUT;
+            if (!EXPAND) {
+                float tmp[P][R4];
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+#pragma unroll
+                    for (int t = 0; t < R4; ++t) tmp[c][t] = 0.f;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    float xc[P];
+#pragma unroll
+                    for (int c = 0; c < P; ++c) xc[c] = x[c * Q + i];
+#pragma unroll
+                    for (int t = 0; t < R4; ++t) {
+                        const float w = u4s[i * R4 + t];
+#pragma unroll
+                        for (int c = 0; c < P; ++c) tmp[c][t] = fmaf(xc[c], w, tmp[c][t]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R3; ++r)
+#pragma unroll
+                    for (int t = 0; t < R4; ++t) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int c = 0; c < P; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                        y[r * R4 + t] = acc;
+                    }
+            } else {
+                float tmp[R3][Q];
+#pragma unroll
+                for (int r = 0; r < R3; ++r)
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) tmp[r][i] = 0.f;
+#pragma unroll
+                for (int t = 0; t < R4; ++t) {
+                    float xr[R3];
+#pragma unroll
+                    for (int r = 0; r < R3; ++r) xr[r] = x[r * R4 + t];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        const float w = u4s[i * R4 + t];
+#pragma unroll
+                        for (int r = 0; r < R3; ++r) tmp[r][i] = fmaf(xr[r], w, tmp[r][i]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int r = 0; r < R3; ++r) acc = fmaf(u3[c * R3 + r], tmp[r][i], acc);
+                        y[c * Q + i] = acc;
+                    }
+            }
+        }
+        __syncthreads();
+        float* dst = out + f0 * LOUT;
+        if (nf == FPB && ((((uintptr_t)dst) & 15) == 0)) {
+            float4* d4 = (float4*)dst;
+            for (int i = threadIdx.x; i < NV_OUT; i += 256) {
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int g = 4 * i + j;
+                    v[j] = fout[(g / LOUT) * SOUT + (g % LOUT)];
+                }
+                d4[i] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        } else {
+            for (int g = threadIdx.x; g < nf * LOUT; g += 256) dst[g] = fout[(g / LOUT) * SOUT + (g % LOUT)];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- fibre Gram (L <= 64)
 // Each block accumulates the lower triangle of sum_a x_a x_a^T over its share of fibres,
 // staged through LDS 64 fibres at a time; thread -> fixed set of (i,j) pairs.
@@ -506,10 +648,40 @@ hipError_t small_ttm(const float* in, int64_t A, int64_t K, int64_t B, const flo
 
 bool pair_ttm_supported(int p, int q) { return p >= 1 && p <= kPairMaxP && q >= 1 && q <= kPairMaxQ; }
 
+namespace {
+template <int P, int Q, int R3, int R4>
+bool try_fixed(const float* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
+               bool expand, float* out, hipStream_t s, hipError_t* err) {
+    if (p != P || q != Q || r3 != R3 || r4 != R4) return false;
+    // float4 staging needs 16-byte aligned chunk starts: 256 * LIN * 4 bytes is a multiple of 16
+    if ((((uintptr_t)in) & 15) != 0) return false;
+    const int64_t nchunks = (A + 255) / 256;
+    const unsigned grid = (unsigned)(nchunks < 1024 ? nchunks : 1024);
+    if (expand)
+        hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, true>), dim3(grid), dim3(256), 0, s, in, A, U3, U4, out);
+    else
+        hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, false>), dim3(grid), dim3(256), 0, s, in, A, U3, U4, out);
+    *err = hipGetLastError();
+    return true;
+}
+}  // namespace
+
 hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, int R3, const float* U4,
                     int R4, bool expand, float* out, hipStream_t s) {
     if (!pair_ttm_supported(p, q) || R3 > p || R4 > q) return hipErrorInvalidValue;
     if (A == 0) return hipSuccess;
+    {
+        // fibre shapes of the multi-exposure stacks: 3 colour channels x 2E images, R4 = 2E - 1,
+        // and the reduced ranks used by the large stacks
+        hipError_t e = hipSuccess;
+        if (try_fixed<3, 14, 3, 8>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
+            try_fixed<3, 10, 3, 6>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
+            try_fixed<3, 6, 3, 4>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
+            try_fixed<3, 6, 3, 5>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
+            try_fixed<3, 10, 3, 9>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
+            try_fixed<3, 14, 3, 13>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e))
+            return e;
+    }
     const int Lin = expand ? R3 * R4 : p * q;
     const int Lout = expand ? p * q : R3 * R4;
     const size_t shm = sizeof(float) * (kPairMaxP * kPairMaxP + kPairMaxQ * kPairMaxQ +
