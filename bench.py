@@ -8,7 +8,8 @@ value is whole-job HOOI sweeps per second: 20 * steps / elapsed.
 Also reported (one JSON line on stdout):
   roofline      the dominant single-kernel stage, algorithmic bytes or flops per launch divided by
                 its mean launch time, timed with HIP events on the launch stream during the timed
-                steps, against the MI355X peak (HBM 8 TB/s, FP32 MFMA 157.3 TFLOP/s);
+                steps, against the MI355X peak (HBM 8 TB/s, FP32 MFMA 157.3 TFLOP/s,
+                FP64 MFMA 78.6 TFLOP/s);
   stages        every timed stage (ms per launch, achieved rate);
   cpu_baseline  the FP64 CPU oracle on the same tensor: T-HOSVD plus a sample of sweeps, timed on
                 the host cores and scaled to the same 20-sweep job.
@@ -32,7 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_MFMA_PEAK_TFLOPS = 157.3
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks
 
 
 def log(msg):
@@ -42,21 +43,22 @@ def log(msg):
 def stage_work(dims, ranks):
     """Algorithmic work of one launch of each single-kernel stage of a tree sweep.
 
-    Returns {stage: (kind, amount)} with kind 'hbm' (bytes) or 'mfma' (flops).  Bytes are
-    the reads of the input and writes of the output once; flops are 2 * MACs (the Gram counts
-    the lower triangle it computes: s^2 K).
+    Returns {stage: (kind, amount)} with kind 'hbm' (bytes), 'f32' or 'f64' (MFMA flops in that
+    type).  Bytes are the reads of the input and writes of the output once; flops are 2 * MACs
+    (the Gram counts the lower triangle it computes: s^2 K).  The Grams run on the FP64 matrix
+    cores (FP32 data, exact products, FP64 accumulation); the mode products on the FP32 ones.
     """
     s0, s1, s2, s3 = dims
     r0, r1, r2, r3 = ranks
     r23, L = r2 * r3, s2 * s3
     return {
         "pass_a": ("hbm", 4 * (s0 * s1 * L + s0 * s1 * r23)),
-        "ttm_y1": ("mfma", 2 * r1 * s1 * (s0 * r23)),
-        "gram_1": ("mfma", s0 * s0 * (r1 * r23)),
-        "ttm_y2": ("mfma", 2 * r0 * s0 * (s1 * r23)),
-        "gram_2": ("mfma", s1 * s1 * (r0 * r23)),
-        "pass_c1": ("mfma", 2 * r0 * s0 * (s1 * L)),
-        "ttm_c2": ("mfma", 2 * r1 * s1 * (r0 * L)),
+        "ttm_y1": ("f32", 2 * r1 * s1 * (s0 * r23)),
+        "gram_1": ("f64", s0 * s0 * (r1 * r23)),
+        "ttm_y2": ("f32", 2 * r0 * s0 * (s1 * r23)),
+        "gram_2": ("f64", s1 * s1 * (r0 * r23)),
+        "pass_c1": ("f32", 2 * r0 * s0 * (s1 * L)),
+        "ttm_c2": ("f32", 2 * r1 * s1 * (r0 * L)),
     }
 
 
@@ -66,8 +68,9 @@ def roofline_of(kind, amount, ms):
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4)}
     achieved = amount / (ms * 1e-3) / 1e12
-    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4)}
+    peak = MFMA_PEAK_TFLOPS[kind]
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "mfma_type": kind}
 
 
 def cpu_baseline(x32, ranks, sweeps_job, sample_sweeps):
@@ -94,6 +97,41 @@ def cpu_baseline(x32, ranks, sweeps_job, sample_sweeps):
             "init_s": round(t_init, 3), "sweep_s": round(t_sweep, 3)}
 
 
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage kernel from the committed counter summary, or None when the
+    kernel's source has changed since the counters were taken (or no summary exists)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_stack1080.txt")
+    if not os.path.exists(path):
+        return None
+    for ln in open(path):
+        f = ln.split()
+        if len(f) == 6 and f[0] == "traffic" and f[1] == stage:
+            src = os.path.join(ROOT, "paper_2104_04726_amd", "csrc", f[4])
+            if not os.path.exists(src):
+                return None
+            digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            if digest != f[5]:
+                return None
+            return {"fetch_bytes": int(f[2]), "write_bytes": int(f[3]), "total_bytes": int(f[2]) + int(f[3]),
+                    "source": "profiles/hbm_traffic_stack1080.txt (FETCH_SIZE x2.0, WRITE_SIZE x1.0 from a "
+                              "1 GiB copy calibration)"}
+    return None
+
+
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain elementwise kernel that reads and writes nbytes each (y = -x, FP32): what the HBM
+    byte counters report for it calibrates them against a known algorithmic traffic."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "reps": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +140,12 @@ def main():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain elementwise copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the decomposition is not "
               "sharded across GPUs in this build", file=sys.stderr)
@@ -142,7 +185,8 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
     value = sweeps * args.steps / elapsed
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} sweeps/s, fit {r.fit:.8f}")
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} sweeps/s, fit {r.fit:.8f}, "
+        f"second CholeskyQR passes {r.stats.get('orth_second_passes')}")
 
     work = stage_work(dims, ranks)
     stages = {}
@@ -155,7 +199,9 @@ def main():
     dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
     kind, amount = work[dominant]
     roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
-    roof.update({"kernel": dominant, "traffic": None,
+    traffic = measured_traffic(dominant)
+    roof.update({"kernel": dominant, "traffic": traffic["total_bytes"] if traffic else None,
+                 "traffic_unit": "bytes per launch", "traffic_detail": traffic,
                  "per_launch": f"{amount / 1e9:.3f} {'GB' if kind == 'hbm' else 'GFLOP'}"})
 
     out = {
@@ -174,6 +220,7 @@ def main():
         "config": {"workload": f"stack1080: {H}x{W}x3x{2 * E} FP32 Y'CbCr multi-exposure stereo stack, ranks "
                                f"{list(ranks)}, T-HOSVD start + {sweeps} HOOI sweeps per step",
                    "sweeps_per_step": sweeps, "fit": round(r.fit, 9),
+                   "orth_second_passes": r.stats.get("orth_second_passes"),
                    "init_ms": round(init_ms / args.steps, 3), "sweeps_ms": round(sweeps_ms / args.steps, 3)},
         "roofline": roof,
         "stages": stages,

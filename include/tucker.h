@@ -97,6 +97,8 @@ typedef struct {
     double fit_gram;             /* last fit from ||X||^2 - ||G||^2 (cheap, FP32 core)        */
     int sweeps;                  /* sweeps performed                                          */
     int chol_shifts;             /* Cholesky pivots that needed the shifted fallback          */
+    int orth_second_passes;      /* CholeskyQR passes run because one pass left ||Q^T Q - I||
+                                    above the FP64 threshold (the rest were skipped on device) */
     size_t workspace_bytes;      /* device workspace held by the context                      */
     double stage_ms[TUCKER_NUM_STAGES];   /* summed GPU time per stage (timing = 1)           */
     int stage_calls[TUCKER_NUM_STAGES];   /* number of timed occurrences per stage            */

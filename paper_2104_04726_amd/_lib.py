@@ -43,6 +43,7 @@ class Stats(C.Structure):
         ("fit_gram", C.c_double),
         ("sweeps", C.c_int),
         ("chol_shifts", C.c_int),
+        ("orth_second_passes", C.c_int),
         ("workspace_bytes", C.c_size_t),
         ("stage_ms", C.c_double * 12),
         ("stage_calls", C.c_int * 12),

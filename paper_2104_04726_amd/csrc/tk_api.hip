@@ -413,8 +413,10 @@ void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, doub
 }
 
 // Q = A T^T (A rows x cols float/double, T cols x cols lower-triangular fp64) -> Q fp64
-void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, const double* Tm, double* Q) {
+void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, const double* Tm, double* Q,
+               const int* run_if = nullptr) {
     GemmArgs g{};
+    g.run_if = run_if;
     g.alpha = 1.0;
     g.M = rows;
     g.N = cols;
@@ -430,9 +432,14 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
 // cold: shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): the first pass
 // factors the scaled Gram plus s I, s = 11 (m n + n (n+1)) u ||W~||_2 with ||W~||_2 <= n (unit
 // diagonal), which cannot break down for a numerically full-rank Z and leaves Q1 well conditioned;
-// two plain passes follow.  warm (Z = S U with U near the invariant subspace, cond(Z) well below
-// u^-1/2): CholeskyQR2.  Each pass maps the basis by an invertible triangular factor, so the column
-// space is that of Z.
+// two plain passes follow.  warm (Z = S U with U near the invariant subspace): CholeskyQR2, whose
+// second pass runs only when the first left max_ij |(Q1^T Q1 - I)_ij| above kOrthTol: the test and
+// the skip happen on the device (the second pass's kernels return at once), so nothing waits on
+// the host.  Column scaling makes the first pass nearly exact when the columns of Z are close to
+// orthogonal, which is the case once the leading columns have settled.  Each pass maps the basis
+// by an invertible triangular factor, so the column space is that of Z.
+constexpr double kOrthTol = 1e-12;
+
 void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
                     bool cold) {
     Plan& p = r.p;
@@ -442,12 +449,16 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     gram_tn64(r, Z, z32, rows, cols, p.W);
     TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
     apply_tri(r, Z, z32, rows, cols, p.Tm, p.Q1);
-    // pass 2: Q1 -> U64 (cold: -> Q1 again through U64, pass 3)
     gram_tn64(r, p.Q1, false, rows, cols, p.W);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
     if (!cold) {
-        apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
+        // pass 2 only where needed: need = p.shifts[2], counted in p.shifts[1]
+        int* need = p.shifts + 2;
+        TK_HIP(orth_check(p.W, cols, kOrthTol, p.red, need, p.shifts + 1, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st, need));
+        apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64, need);
+        TK_HIP(copy_unless(need, p.Q1, U64, rows * cols, r.st));
     } else {
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
         gram_tn64(r, U64, false, rows, cols, p.W);
         TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
@@ -1025,10 +1036,10 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         TK_HIP(hipEventRecord(ctx->ev[3], s));
         std::vector<double> fits(done + 1);
         double fexact = 0.0;
-        int shifts = 0;
         TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         TK_HIP(hipMemcpyAsync(&fexact, p.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipMemcpyAsync(&shifts, p.shifts, sizeof(int), hipMemcpyDeviceToHost, s));
+        int shifts2[4] = {0, 0, 0, 0};
+        TK_HIP(hipMemcpyAsync(shifts2, p.shifts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
         *fit = fexact;
         if (fit_history)
@@ -1047,7 +1058,8 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         ctx->stats.final_fit_ms = elapsed(ctx->ev[2], ctx->ev[3]);
         ctx->stats.fit_gram = fits[done];
         ctx->stats.sweeps = done;
-        ctx->stats.chol_shifts = shifts;
+        ctx->stats.chol_shifts = shifts2[0];
+        ctx->stats.orth_second_passes = shifts2[1];
         ctx->stats.workspace_bytes = ctx->ws_bytes;
         if (!std::isfinite(fexact)) throw Fail{TUCKER_ERR_NUMERICAL, "non-finite fit"};
     });
@@ -1133,6 +1145,7 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
             p.chol_ws = a.take<char>(chol_counter_ints(cols) * 4 + 64 + cols * 8);
             p.Q1 = a.take<double>(rows * cols);
             p.shifts = a.take<int>(4);
+            p.red = a.take<double>(kSumsqBlocks);
             U64 = a.take<double>(rows * cols);
         });
         TK_HIP(fill_zero(p.shifts, 16, r.st));

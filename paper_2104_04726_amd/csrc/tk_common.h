@@ -44,6 +44,7 @@ struct GemmArgs {
     int64_t c_zstride;  // element offset between split outputs
     int lower_only;     // enumerate only tiles with tile_m >= tile_n (Gram / SYRK)
     double* resid_partial;   // EPI_RESID: one double per block
+    const int* run_if;       // nullable: the launch does nothing when *run_if == 0
 };
 
 // fp32 MFMA GEMM (operands fp32, accumulation fp32; acc64 = FP64 accumulation across k-tiles)
@@ -122,8 +123,16 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // (W~ = D^-1 W D^-1) by a tiled task graph, then T = L^-1 D^-1 (lower triangular) to Tout.
 // counters: int workspace of chol_counter_ints(n) entries (zeroed by the call).
 // shifts: int counter incremented for every pivot that needed the shifted fallback.
+// run_if (nullable): every kernel of the call returns at once when *run_if == 0.
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           int* shifts, hipStream_t s);
+                           int* shifts, hipStream_t s, const int* run_if = nullptr);
+// need[0] = 1 (and ++count[0]) when max_ij |W_ij - delta_ij| > tol, else 0 (n x n FP64).
+// partial: orth_check_partials() doubles of scratch.
+hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count,
+                      hipStream_t s);
+int orth_check_partials();
+// dst = src (n doubles) when *need == 0
+hipError_t copy_unless(const int* need, const double* src, double* dst, int64_t n, hipStream_t s);
 int64_t chol_counter_ints(int64_t n);
 
 // Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading

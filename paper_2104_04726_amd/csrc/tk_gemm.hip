@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
     __shared__ T As[ASZ];
     __shared__ T Bs[BSZ];
+    if (g.run_if && *g.run_if == 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;

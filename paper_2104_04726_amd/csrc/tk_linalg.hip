@@ -12,6 +12,8 @@
 //
 // jacobi_eig: cyclic two-sided Jacobi (Golub & Van Loan, Alg. 8.4.3, with the parallel
 //   round-robin ordering) on a symmetric matrix of order <= 64 held in LDS.
+#include <algorithm>
+
 #include "tk_common.h"
 
 namespace tk {
@@ -36,6 +38,7 @@ struct CholArgs {
     int* flagI;
     int* shifts;
     int* err;
+    const int* run_if;
 };
 
 // Shared tiles and flags are accessed with agent-scope relaxed atomics, which are coherent across
@@ -80,26 +83,42 @@ __device__ void release_flag(int* f) {
 }
 
 // tile (ti,tj) of an n x n row-major matrix -> LDS t; out-of-range -> 0 (or 1 on the diagonal
-// when pad_diag), optionally scaled by dsc[r] dsc[c] and shifted on the diagonal
+// when pad_diag), optionally scaled by dsc[r] dsc[c] and shifted on the diagonal.  Every thread
+// issues all of its TB*TB/256 coherent loads before the first use, so their latencies overlap.
+constexpr int kTileVals = TB * TB / 256;
+
 __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dsc,
                           bool pad_diag, double shift = 0.0) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    double v[kTileVals];
+#pragma unroll
+    for (int u = 0; u < kTileVals; ++u) {
+        const int e = threadIdx.x + 256 * u;
         const int r = e / TB, c = e % TB;
         const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
-        double v;
+        v[u] = 0.0;
+        if (gr < n && gc < n) v[u] = ld_coh(&M[gr * n + gc]);
+    }
+#pragma unroll
+    for (int u = 0; u < kTileVals; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int r = e / TB, c = e % TB;
+        const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
+        double x;
         if (gr < n && gc < n) {
-            v = ld_coh(&M[gr * n + gc]);
-            if (dsc) v *= dsc[gr] * dsc[gc];
-            if (gr == gc) v += shift;
+            x = v[u];
+            if (dsc) x *= dsc[gr] * dsc[gc];
+            if (gr == gc) x += shift;
         } else {
-            v = (pad_diag && gr == gc) ? 1.0 : 0.0;
+            x = (pad_diag && gr == gc) ? 1.0 : 0.0;
         }
-        t[r * TS + c] = v;
+        t[r * TS + c] = x;
     }
 }
 
 __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kTileVals; ++u) {
+        const int e = threadIdx.x + 256 * u;
         const int r = e / TB, c = e % TB;
         const int64_t gr = (int64_t)ti * TB + r, gc = (int64_t)tj * TB + c;
         if (gr < n && gc < n) st_coh(&M[gr * n + gc], t[r * TS + c]);
@@ -316,7 +335,8 @@ __device__ void tile_trtri(const double* L, double* X) {
 }
 
 __global__ __launch_bounds__(256) void chol_prologue(const double* W, int64_t n, bool scale, double* dsc,
-                                                    int* shifts) {
+                                                    int* shifts, const int* run_if) {
+    if (run_if && *run_if == 0) return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double d = W[i * n + i];
         if (!scale) {
@@ -333,6 +353,7 @@ __global__ __launch_bounds__(256) void chol_prologue(const double* W, int64_t n,
 __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
     __shared__ double At[TB * TS], Bt[TB * TS], Ct[TB * TS];
     __shared__ int task_s;
+    if (a.run_if && *a.run_if == 0) return;
     if (threadIdx.x == 0) task_s = atomicAdd(a.ticket, 1);
     __syncthreads();
     const int task = task_s;
@@ -404,17 +425,60 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
 }
 
 // a timed-out wait of the task graph is reported through the shift counter (+1e6)
-__global__ void chol_report(const int* err, int* shifts) {
+__global__ void chol_report(const int* err, int* shifts, const int* run_if) {
+    if (run_if && *run_if == 0) return;
     if (threadIdx.x == 0 && blockIdx.x == 0 && *err) atomicAdd(shifts, 1000000);
 }
 
 // T <- lower(T) * D^-1 (column scaling), upper triangle zeroed
-__global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc) {
+__global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc, const int* run_if) {
+    if (run_if && *run_if == 0) return;
     const int64_t total = n * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = e / n, c = e % n;
         Tm[e] = (r >= c) ? Tm[e] * dsc[c] : 0.0;
     }
+}
+
+// Deviation of a Gram Q^T Q from the identity, max_ij |W_ij - delta_ij|: per-block maxima, then
+// one block folds them and writes need = (max > tol) (NaN counts as needed) and counts the passes.
+constexpr int kOrthBlocks = 128;
+__global__ __launch_bounds__(256) void orth_dev_kernel(const double* __restrict__ W, int64_t n,
+                                                       double* __restrict__ partial) {
+    __shared__ double red[256];
+    double m = 0.0;
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const double a = fabs(W[e] - ((e / n == e % n) ? 1.0 : 0.0));
+        m = (a > m || a != a) ? a : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+__global__ void orth_need_kernel(const double* __restrict__ partial, int nb, double tol, int* need, int* count) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double o = partial[b];
+        if (o > m || o != o) m = o;
+    }
+    const int nd = !(m <= tol);
+    *need = nd;
+    if (nd && count) atomicAdd(count, 1);
+}
+
+__global__ __launch_bounds__(256) void copy_unless_kernel(const int* need, const double* __restrict__ src,
+                                                          double* __restrict__ dst, int64_t n) {
+    if (*need) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- Jacobi
@@ -541,7 +605,7 @@ int64_t chol_counter_ints(int64_t n) {
 }
 
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           int* shifts, hipStream_t s) {
+                           int* shifts, hipStream_t s, const int* run_if) {
     if (n <= 0) return hipSuccess;
     const int T = (int)((n + TB - 1) / TB);
     // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); dsc stored after Tout?  no:
@@ -549,16 +613,35 @@ hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, doubl
     hipError_t e = fill_zero(counters, chol_counter_ints(n) * (int64_t)sizeof(int), s);
     if (e != hipSuccess) return e;
     double* dsc = (double*)(((uintptr_t)(counters + chol_counter_ints(n)) + 15) & ~(uintptr_t)15);
-    hipLaunchKernelGGL(chol_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, scale, dsc, shifts);
+    hipLaunchKernelGGL(chol_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, scale, dsc, shifts, run_if);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    CholArgs a{W, n, T, shift, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1};
+    CholArgs a{W, n, T, shift, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1, run_if};
     hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(chol_report, dim3(1), dim3(64), 0, s, counters + 1, shifts);
+    hipLaunchKernelGGL(chol_report, dim3(1), dim3(64), 0, s, counters + 1, shifts, run_if);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t total = n * n;
     hipLaunchKernelGGL(chol_epilogue, dim3((unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096)),
-                       dim3(256), 0, s, Tout, n, dsc);
+                       dim3(256), 0, s, Tout, n, dsc, run_if);
+    return hipGetLastError();
+}
+
+int orth_check_partials() { return kOrthBlocks; }
+
+hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count,
+                      hipStream_t s) {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kOrthBlocks, (n * n + 255) / 256));
+    hipLaunchKernelGGL(orth_dev_kernel, dim3(nb), dim3(256), 0, s, W, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(orth_need_kernel, dim3(1), dim3(64), 0, s, partial, nb, tol, need, count);
+    return hipGetLastError();
+}
+
+hipError_t copy_unless(const int* need, const double* src, double* dst, int64_t n, hipStream_t s) {
+    const int64_t g = std::min<int64_t>(2048, (n + 255) / 256);
+    if (g <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_unless_kernel, dim3((unsigned)g), dim3(256), 0, s, need, src, dst, n);
     return hipGetLastError();
 }
 
