@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
+                    help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -164,7 +166,7 @@ def main():
     x = torch.from_numpy(x32).to("cuda:0")
     torch.cuda.synchronize()
 
-    ctx = tk.Context(0, timing=True)
+    ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
@@ -215,10 +217,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8": "fp8_e4m3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"stack1080: {H}x{W}x3x{2 * E} FP32 Y'CbCr multi-exposure stereo stack, ranks "
-                               f"{list(ranks)}, T-HOSVD start + {sweeps} HOOI sweeps per step",
+                               f"{list(ranks)}, T-HOSVD start + {sweeps} HOOI sweeps per step"
+                               + ("" if args.precision == "fp32" else
+                                  f" ({args.precision} contractions, then 1 FP32 refinement sweep)"),
+                   "precision": args.precision,
                    "sweeps_per_step": sweeps, "fit": round(r.fit, 9),
                    "orth_second_passes": r.stats.get("orth_second_passes"),
                    "init_ms": round(init_ms / args.steps, 3), "sweeps_ms": round(sweeps_ms / args.steps, 3)},

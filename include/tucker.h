@@ -48,8 +48,15 @@ typedef enum {
     TUCKER_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement        */
 } tucker_status;
 
-/* Operand precision of the TTM and Gram contractions (accumulation is always FP32; the
- * orthogonalisation and the norms are FP64 whatever the choice). */
+/* Operand precision of the TTM and Gram contractions of the sweeps (the precision variants of the
+ * HOOI sweep, eq. (8)).  Accumulation is always FP32; the orthogonalisation and the norms are FP64
+ * and the T-HOSVD start uses the FP32 tensor whatever the choice.  BF16 / FP16: X and the sweep
+ * intermediates are stored in that type (round to nearest even).  FP8_E4M3: X is stored in the OCP
+ * E4M3 format with one FP32 scale per slice of the two trailing modes (amax / 448) and multiplied
+ * on the FP8 matrix cores in the two full-tensor products; the intermediates are BF16.  After the
+ * reduced-precision sweeps, refine_sweeps FP32 sweeps run on the FP32 tensor.  Reduced precision
+ * needs an order-4 tensor whose two leading modes are larger than 64 and whose two trailing modes
+ * are small (the image stacks); other shapes return TUCKER_ERR_UNSUPPORTED. */
 typedef enum {
     TUCKER_FP32 = 0,
     TUCKER_BF16 = 1,
@@ -95,7 +102,8 @@ typedef struct {
     double sweeps_ms;            /* all ALS sweeps, GPU time                                  */
     double final_fit_ms;         /* exact-residual fit and output copies, GPU time            */
     double fit_gram;             /* last fit from ||X||^2 - ||G||^2 (cheap, FP32 core)        */
-    int sweeps;                  /* sweeps performed                                          */
+    int sweeps;                  /* sweeps performed (reduced precision: excluding refinement) */
+    int refine_sweeps;           /* FP32 refinement sweeps after reduced-precision ones       */
     int chol_shifts;             /* Cholesky pivots that needed the shifted fallback          */
     int orth_second_passes;      /* CholeskyQR passes run because one pass left ||Q^T Q - I||
                                     above the FP64 threshold (the rest were skipped on device) */
@@ -172,6 +180,27 @@ tucker_status tucker_ttm(tucker_ctx* ctx, const float* in, int ndim, const int64
  * out device dims[mode]^2 floats, symmetric, row-major.  Stream-ordered. */
 tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims,
                           int mode, float* out);
+
+/* Reduced-precision encoding round trip, the storage step of the precision variants: x is a
+ * rows x L row-major matrix (device floats); out[i] = dec(enc(x[i] / s[i % L])) * s[i % L] with
+ * s = 1 for BF16 / FP16 (round to nearest even) and, for FP8_E4M3 (OCP E4M3, saturating at 448),
+ * s[l] = max_rows |x[., l]| / 448 (1 for an all-zero column), written to scales (device L floats,
+ * required for FP8, ignored otherwise).  L <= 256.  Stream-ordered. */
+tucker_status tucker_quantize(tucker_ctx* ctx, const float* x, int64_t rows, int64_t L,
+                              tucker_precision precision, float* out, float* scales);
+
+/* Mode product in reduced precision (eq. (8) on the BF16 / FP16 / FP8 matrix cores, FP32
+ * accumulation): out = Q(in) x_mode Q(U)^T with the same shapes as tucker_ttm.  Q encodes as
+ * tucker_quantize does; for FP8 the tensor is scaled per index of its last mode and U per column,
+ * and mode must not be the last one.  Stream-ordered. */
+tucker_status tucker_ttm_lowp(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims,
+                              int mode, const float* U, int64_t r, tucker_precision precision,
+                              float* out);
+
+/* Mode-n Gram of Q(in) on the BF16 / FP16 matrix cores (FP32 accumulation within K splits, the
+ * splits summed in FP64); out as for tucker_gram.  Stream-ordered. */
+tucker_status tucker_gram_lowp(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims,
+                               int mode, tucker_precision precision, float* out);
 
 /* Orthonormal basis of the column space of Z (rows x cols, rows >= cols) by FP64
  * CholeskyQR2 with column scaling.  Z, Q device floats, row-major; Q may alias Z.

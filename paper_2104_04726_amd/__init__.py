@@ -188,6 +188,43 @@ class Context:
                                       C.c_void_p(out.data_ptr())), self._h)
         return out
 
+    def quantize(self, x, precision: str):
+        """Encode/decode round trip of a (rows, L) matrix; returns (values, scales or None)."""
+        import torch
+        x = _f32_device(x, "x")
+        if x.dim() != 2:
+            raise ValueError("x must be 2-D (rows, L)")
+        out = torch.empty_like(x)
+        scales = torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
+        _check(_lib.lib().tucker_quantize(self._h, C.c_void_p(x.data_ptr()), int(x.shape[0]), int(x.shape[1]),
+                                          _PRECISIONS[precision], C.c_void_p(out.data_ptr()),
+                                          C.c_void_p(scales.data_ptr())), self._h)
+        return out, (scales if precision == "fp8" else None)
+
+    def ttm_lowp(self, x, mode: int, U, precision: str):
+        """Q(x) x_mode Q(U)^T on the reduced-precision matrix cores (float result)."""
+        import torch
+        x = _f32_device(x, "x")
+        U = _f32_device(U, "U")
+        dims = list(x.shape)
+        out_dims = list(dims)
+        out_dims[mode] = int(U.shape[1])
+        out = torch.empty(out_dims, dtype=torch.float32, device=x.device)
+        _check(_lib.lib().tucker_ttm_lowp(self._h, C.c_void_p(x.data_ptr()), len(dims), _lib.i64(dims), int(mode),
+                                          C.c_void_p(U.data_ptr()), int(U.shape[1]), _PRECISIONS[precision],
+                                          C.c_void_p(out.data_ptr())), self._h)
+        return out
+
+    def gram_lowp(self, x, mode: int, precision: str):
+        """Mode Gram of Q(x) on the BF16 / FP16 matrix cores (float result)."""
+        import torch
+        x = _f32_device(x, "x")
+        dims = list(x.shape)
+        out = torch.empty((dims[mode], dims[mode]), dtype=torch.float32, device=x.device)
+        _check(_lib.lib().tucker_gram_lowp(self._h, C.c_void_p(x.data_ptr()), len(dims), _lib.i64(dims), int(mode),
+                                           _PRECISIONS[precision], C.c_void_p(out.data_ptr())), self._h)
+        return out
+
     def orthonormalize(self, Z):
         import torch
         Z = _f32_device(Z, "Z")

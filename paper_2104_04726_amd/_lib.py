@@ -42,6 +42,7 @@ class Stats(C.Structure):
         ("final_fit_ms", C.c_double),
         ("fit_gram", C.c_double),
         ("sweeps", C.c_int),
+        ("refine_sweeps", C.c_int),
         ("chol_shifts", C.c_int),
         ("orth_second_passes", C.c_int),
         ("workspace_bytes", C.c_size_t),
@@ -85,8 +86,12 @@ def _declare(lib):
     lib.tucker_last_error.argtypes = [v]
     lib.tucker_last_error.restype = C.c_char_p
     lib.tucker_get_stats.argtypes = [v, C.POINTER(Stats)]
+    lib.tucker_quantize.argtypes = [v, v, C.c_int64, C.c_int64, C.c_int, v, v]
+    lib.tucker_ttm_lowp.argtypes = [v, v, C.c_int, I64P, C.c_int, v, C.c_int64, C.c_int, v]
+    lib.tucker_gram_lowp.argtypes = [v, v, C.c_int, I64P, C.c_int, C.c_int, v]
     for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
                  "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
+                 "tucker_quantize", "tucker_ttm_lowp", "tucker_gram_lowp",
                  "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv", "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):
         getattr(lib, name).restype = C.c_int
 

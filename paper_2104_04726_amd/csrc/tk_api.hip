@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "tk_common.h"
+#include "tk_lowp.h"
 #include "../../include/tucker.h"
 
 using namespace tk;
@@ -92,6 +93,15 @@ struct Plan {
     ModeKind kind[TUCKER_MAX_ORDER]{};
     bool tree = false;
     int max_iters = 0;
+    int refine = 0;          // FP32 sweeps after reduced-precision ones
+    // reduced-precision sweeps (tree shapes): storage type of X (prec) and of the intermediates (ip)
+    int prec = 0, ip = 0;
+    int64_t R23p = 0;        // R3 R4 rounded up to 8: padded fibre length of T34 / Y0 / Y1
+    void *Xlp = nullptr, *T34lp = nullptr, *Y0lp = nullptr, *Y1lp = nullptr, *T1lp = nullptr;
+    void *U1t = nullptr, *U2t = nullptr, *U1t8 = nullptr;   // transposed factor copies (rows padded to 8)
+    float *xscale = nullptr, *u1scale = nullptr, *spart = nullptr;
+    float* Pf = nullptr;     // FP32 Gram partials
+    int64_t Pf_elems = 0;
 
     float* U32[TUCKER_MAX_ORDER]{};
     double* U64[TUCKER_MAX_ORDER]{};
@@ -165,6 +175,23 @@ int64_t chain_max(const Plan& p) {
 }
 
 constexpr int kGramTargetBlocks = 1024;
+constexpr int kLpScaleBlocks = 256;
+constexpr int kRefineInner = 4;
+constexpr int kLpGramTargetBlocks = 512;
+
+// split-K of a reduced-precision Gram (128 x 128 tiles, lower triangle; k_split a multiple of 64)
+int64_t lp_gram_ksplit(int64_t s, int64_t K) {
+    const int64_t t = (s + 127) / 128;
+    const int64_t tiles = t * (t + 1) / 2;
+    int64_t sp = std::max<int64_t>(1, (kLpGramTargetBlocks + tiles - 1) / tiles);
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 512));
+    int64_t ks = (K + sp - 1) / sp;
+    return (ks + 63) / 64 * 64;
+}
+int64_t lp_gram_partials(int64_t s, int64_t K) {
+    const int64_t ks = lp_gram_ksplit(s, K);
+    return ((K + ks - 1) / ks) * s * s;
+}
 
 int gram_splits(int64_t s, int64_t K) {
     const int64_t t = (s + 63) / 64;       // 64 x 64 FP64 MFMA tiles
@@ -191,6 +218,25 @@ void build_plan(Plan& p, Arena& a) {
         p.T12 = a.take<float>(p.R[0] * p.R[1] * L);
         p.F = a.take<double>(64 * 64);
         p.Fpart = a.take<double>(std::max<int64_t>((int64_t)kFibreGramBlocks * L * L, 64 * 64 * 64));
+        if (p.prec != 0) {
+            const int es = (p.prec == TUCKER_FP8_E4M3) ? 1 : 2;
+            const int64_t R0 = p.R[0], R1 = p.R[1];
+            const int64_t s0p = (s0 + 7) / 8 * 8, s1p = (s1 + 7) / 8 * 8;
+            p.R23p = (R23 + 7) / 8 * 8;
+            p.Xlp = a.take<char>(Xn * es);
+            p.xscale = a.take<float>(L);
+            p.spart = a.take<float>(kLpScaleBlocks * L);
+            p.T34lp = a.take<uint16_t>(s0 * s1 * p.R23p);
+            p.Y0lp = a.take<uint16_t>(s0 * R1 * p.R23p);
+            p.Y1lp = a.take<uint16_t>(R0 * s1 * p.R23p);
+            p.T1lp = a.take<uint16_t>(R0 * s1 * L);
+            p.U1t = a.take<uint16_t>(R0 * s0p);
+            p.U2t = a.take<uint16_t>(R1 * s1p);
+            p.U1t8 = a.take<uint8_t>(R0 * s0p);
+            p.u1scale = a.take<float>(R0);
+            p.Pf_elems = std::max(lp_gram_partials(s0, R1 * p.R23p), lp_gram_partials(s1, R0 * p.R23p));
+            p.Pf = a.take<float>(p.Pf_elems);
+        }
     } else {
         const int64_t cm = chain_max(p);
         p.Ya = a.take<float>(cm);
@@ -230,7 +276,7 @@ void build_plan(Plan& p, Arena& a) {
     p.rpart_elems = std::max<int64_t>(4096, (Xn / (128 * 128)) + 4096);
     p.rpart = a.take<double>(p.rpart_elems);
     p.scal = a.take<double>(8);
-    p.fits = a.take<double>(p.max_iters + 2);
+    p.fits = a.take<double>(p.max_iters + p.refine + 2);
     p.shifts = a.take<int>(4);
     if (!p.tree) p.Xh = (p.kind[0] == LARGE && p.s[0] > kSmallMode) ? nullptr : a.take<float>(Xn);
 }
@@ -246,6 +292,7 @@ struct Run {
     };
     std::vector<Mark> marks;
     size_t next_ev = 0;
+    int inner_override = 0;     // orthogonal-iteration steps per update in refinement sweeps
 
     int record() {
         if (next_ev >= ctx->pool.size()) {
@@ -500,7 +547,8 @@ void update_factor(Run& r, int n, bool cold) {
         TK_HIP(f32_to_f64(p.U32[n], p.U64[n], p.s[n] * p.R[n], r.st));
         orth_iter(r, n, std::max(1, r.ctx->opt.init_iters), true);
     } else {
-        orth_iter(r, n, std::max(1, r.ctx->opt.inner_iters), false);
+        const int q = r.inner_override > 0 ? std::max(r.inner_override, r.ctx->opt.inner_iters) : r.ctx->opt.inner_iters;
+        orth_iter(r, n, std::max(1, q), false);
     }
 }
 
@@ -615,6 +663,143 @@ void sweep_tree(Run& r) {
         }
     }
     // core G = T12 x_3 U3^T x_4 U4^T
+    StageTimer t(r, TUCKER_STAGE_CORE);
+    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
+}
+
+// ------------------------------------------------------------------ reduced-precision sweep
+// The same tree sweep as sweep_tree with every dense contraction on the 16-/8-bit matrix cores
+// (FP32 accumulation) and the intermediates T34, Y0, Y1, T1 stored in the 16-bit type; the
+// orthogonal iteration, the small modes, the core and all norms are unchanged.  X is converted
+// once per decomposition (FP8: one scale per (channel, image) slice, folded back in pass A and in
+// the epilogue of pass C1).
+
+// X -> Xlp (and the FP8 slice scales)
+void lp_convert_x(Run& r) {
+    Plan& p = r.p;
+    const int64_t L = p.s[2] * p.s[3], Xn = prod(p.s, 0, p.N);
+    const float* scale = nullptr;
+    if (p.prec == TUCKER_FP8_E4M3) {
+        TK_HIP(slice_scales(r.X, Xn / L, (int)L, p.spart, kLpScaleBlocks, p.xscale, r.st));
+        scale = p.xscale;
+    }
+    TK_HIP(to_lowp(r.X, Xn, p.prec, (int)L, scale, p.Xlp, r.st));
+}
+
+// transposed reduced-precision copy of factor n: Ut (R x round8(s)), k contiguous
+void lp_factor(Run& r, int n, int prec, void* Ut, float* scale) {
+    Plan& p = r.p;
+    const int64_t sp = (p.s[n] + 7) / 8 * 8;
+    TK_HIP(factor_lowp(p.U32[n], p.s[n], p.R[n], sp, prec, scale, Ut, r.st));
+}
+
+// mode product out = B x U^T on the matrix cores: A = Ut (M = R rows, K = s), B an n-contiguous view
+void lp_ttm(Run& r, int prec, const void* Ut, int64_t R, int64_t K, Desc b, int64_t N, Desc c, int outp,
+            const float* sa = nullptr, const float* sb = nullptr, int64_t sb_mod = 0) {
+    LpGemmArgs g{};
+    g.a = plain(Ut, (K + 7) / 8 * 8);
+    g.b = b;
+    g.c = c;
+    g.M = R;
+    g.N = N;
+    g.K = K;
+    g.alpha = 1.0;
+    g.k_split = 0;
+    g.sa = sa;
+    g.sb = sb;
+    g.sb_mod = sb_mod;
+    TK_HIP(gemm_lp(g, prec, KM, outp, r.st));
+}
+
+// S64 = Y Y^T for a k-contiguous view Y (s rows, K columns): FP32 partials over K splits, summed in FP64
+void lp_gram(Run& r, Desc y, int64_t srows, int64_t K, int stage) {
+    Plan& p = r.p;
+    LpGemmArgs g{};
+    g.a = y;
+    g.b = y;
+    g.M = srows;
+    g.N = srows;
+    g.K = K;
+    g.alpha = 1.0;
+    g.lower_only = 1;
+    g.k_split = lp_gram_ksplit(srows, K);
+    const int nsplit = (int)((K + g.k_split - 1) / g.k_split);
+    if ((int64_t)nsplit * srows * srows > p.Pf_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer"};
+    g.c = plain(p.Pf, srows);
+    g.c_zstride = srows * srows;
+    {
+        StageTimer t(r, stage);
+        TK_HIP(gemm_lp(g, p.ip, MK, LP_F32OUT, r.st));
+    }
+    StageTimer t(r, stage >= 0 ? TUCKER_STAGE_REDUCE : -1);
+    TK_HIP(gram_reduce(p.Pf, nsplit, srows, srows * srows, nullptr, p.S64, r.st));
+}
+
+void sweep_tree_lp(Run& r) {
+    Plan& p = r.p;
+    const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3];
+    const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3];
+    const int64_t R23p = p.R23p, L = s2 * s3;
+    const int ip = p.ip;
+    // T34 = X x_3 U3^T x_4 U4^T from the reduced-precision X, padded fibres of R23p
+    {
+        StageTimer t(r, TUCKER_STAGE_PASS_A);
+        TK_HIP(pair_lowp(p.Xlp, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, p.prec,
+                         p.prec == TUCKER_FP8_E4M3 ? p.xscale : nullptr, ip, (int)R23p, p.T34lp, r.st));
+    }
+    // mode 1: Y0 = T34 x_2 U2^T (k = w; n = (h, j)), S0 = Y0_(1) Y0_(1)^T
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_Y1);
+        lp_factor(r, 1, ip, p.U2t, nullptr);
+        lp_ttm(r, ip, p.U2t, R1, s1, folded(p.T34lp, R23p, R23p, s1 * R23p), s0 * R23p,
+               folded(p.Y0lp, R23p, R23p, R1 * R23p), ip);
+    }
+    lp_gram(r, plain(p.Y0lp, R1 * R23p), s0, R1 * R23p, TUCKER_STAGE_GRAM_1);
+    {
+        StageTimer t(r, TUCKER_STAGE_OI_1);
+        update_factor(r, 0, false);
+    }
+    // mode 2: Y1 = T34 x_1 U1^T (new U1), S1 from Y1 viewed (R0, s1, R23p)
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_Y2);
+        lp_factor(r, 0, ip, p.U1t, nullptr);
+        lp_ttm(r, ip, p.U1t, R0, s0, plain(p.T34lp, s1 * R23p), s1 * R23p, plain(p.Y1lp, s1 * R23p), ip);
+    }
+    lp_gram(r, folded(p.Y1lp, R23p, R23p, s1 * R23p), s1, R0 * R23p, TUCKER_STAGE_GRAM_2);
+    {
+        StageTimer t(r, TUCKER_STAGE_OI_2);
+        update_factor(r, 1, false);
+    }
+    // T1 = X x_1 U1^T (second pass over X), T12 = T1 x_2 U2^T in FP32
+    {
+        StageTimer t(r, TUCKER_STAGE_PASS_C1);
+        if (p.prec == TUCKER_FP8_E4M3) {
+            lp_factor(r, 0, TUCKER_FP8_E4M3, p.U1t8, p.u1scale);
+            lp_ttm(r, TUCKER_FP8_E4M3, p.U1t8, R0, s0, plain(p.Xlp, s1 * L), s1 * L, plain(p.T1lp, s1 * L), ip,
+                   p.u1scale, p.xscale, L);
+        } else {
+            lp_ttm(r, p.prec, p.U1t, R0, s0, plain(p.Xlp, s1 * L), s1 * L, plain(p.T1lp, s1 * L), ip);
+        }
+    }
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_C2);
+        lp_factor(r, 1, ip, p.U2t, nullptr);
+        lp_ttm(r, ip, p.U2t, R1, s1, folded(p.T1lp, L, L, s1 * L), R0 * L, folded(p.T12, L, L, R1 * L),
+               LP_F32OUT);
+    }
+    // modes 3 and 4 and the core exactly as in the FP32 sweep
+    if (p.kind[2] != FIXED || p.kind[3] != FIXED) {
+        StageTimer t(r, TUCKER_STAGE_SMALL);
+        TK_HIP(fibre_gram(p.T12, R0 * R1, (int)L, p.Fpart, kFibreGramBlocks, p.F, r.st));
+        if (p.kind[2] != FIXED) {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[3], (int)R3, 3, p.S64, r.st));
+            update_factor(r, 2, false);
+        }
+        if (p.kind[3] != FIXED) {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[2], (int)R2, 4, p.S64, r.st));
+            update_factor(r, 3, false);
+        }
+    }
     StageTimer t(r, TUCKER_STAGE_CORE);
     TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
 }
@@ -736,15 +921,22 @@ tucker_status validate_args(int ndim, const int64_t* dims, const int64_t* ranks,
     return TUCKER_OK;
 }
 
-void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int max_iters) {
+void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int max_iters, int prec = 0,
+               int refine = 0) {
     p.N = ndim;
     p.max_iters = max_iters;
+    p.refine = prec ? refine : 0;
     for (int n = 0; n < ndim; ++n) {
         p.s[n] = dims[n];
         p.R[n] = ranks[n];
         p.kind[n] = (ranks[n] == dims[n]) ? FIXED : (dims[n] <= kSmallMode ? SMALL : LARGE);
     }
     p.tree = (ndim == 4) && pair_ttm_supported((int)dims[2], (int)dims[3]) && dims[2] * dims[3] <= 64;
+    p.prec = prec;
+    p.ip = (prec == TUCKER_FP8_E4M3) ? TUCKER_BF16 : prec;
+    if (prec != 0 && !(p.tree && p.kind[0] == LARGE && p.kind[1] == LARGE))
+        throw Fail{TUCKER_ERR_UNSUPPORTED,
+                   "reduced precision needs an order-4 tensor with two large leading modes and small trailing ones"};
 }
 
 size_t plan_bytes(Plan& p) {
@@ -898,9 +1090,13 @@ tucker_status tucker_workspace_size(int ndim, const int64_t* dims, const int64_t
     tucker_status st = validate_args(ndim, dims, ranks, 0, 0.0, why);
     if (st != TUCKER_OK) return st;
     if (!bytes || precision < TUCKER_FP32 || precision > TUCKER_FP8_E4M3) return TUCKER_ERR_INVALID_ARG;
-    Plan p;
-    make_plan(p, ndim, dims, ranks, 0);
-    *bytes = plan_bytes(p);
+    try {
+        Plan p;
+        make_plan(p, ndim, dims, ranks, 0, (int)precision, 1);
+        *bytes = plan_bytes(p);
+    } catch (const Fail& f) {
+        return f.st;
+    }
     return TUCKER_OK;
 }
 
@@ -978,7 +1174,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
     return guarded(ctx, [&]() {
         Run r{ctx, Plan{}, ctx->stream, tensor};
         Plan& p = r.p;
-        make_plan(p, ndim, dims, ranks, max_iters);
+        make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps);
         bind(ctx, p);
         const hipStream_t s = r.st;
         TK_HIP(fill_zero(p.shifts, 16, s));
@@ -1014,8 +1210,11 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         TK_HIP(hipEventRecord(ctx->ev[1], s));
         int done = 0;
         std::vector<double> hf(2);
+        if (p.prec != 0) lp_convert_x(r);
         for (int k = 1; k <= max_iters; ++k) {
-            if (p.tree)
+            if (p.prec != 0)
+                sweep_tree_lp(r);
+            else if (p.tree)
                 sweep_tree(r);
             else
                 sweep_generic(r);
@@ -1027,6 +1226,15 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
                 if (std::fabs(hf[1] - hf[0]) < tol) break;
             }
         }
+        // FP32 refinement sweeps after reduced-precision ones, warm-started from their factors; each
+        // large-mode update iterates to the leading subspace of its FP32 Gram (kRefineInner steps),
+        // since the warm start carries the reduced-precision error
+        r.inner_override = kRefineInner;
+        for (int k = 1; k <= p.refine; ++k) {
+            sweep_tree(r);
+            core_norm_and_fit(r, p.fits + done + k);
+        }
+        r.inner_override = 0;
         TK_HIP(hipEventRecord(ctx->ev[2], s));
         expand_chain(r, p.G, p.U32, nullptr, tensor);
         TK_HIP(fit_from_resid(p.scal + 0, p.scal + 2, p.scal + 3, s));
@@ -1034,9 +1242,10 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         for (int n = 0; n < p.N; ++n)
             TK_HIP(hipMemcpyAsync(factors[n], p.U32[n], p.s[n] * p.R[n] * sizeof(float), hipMemcpyDeviceToDevice, s));
         TK_HIP(hipEventRecord(ctx->ev[3], s));
-        std::vector<double> fits(done + 1);
+        const int total = done + p.refine;
+        std::vector<double> fits(total + 1);
         double fexact = 0.0;
-        TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (total + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         TK_HIP(hipMemcpyAsync(&fexact, p.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
         int shifts2[4] = {0, 0, 0, 0};
         TK_HIP(hipMemcpyAsync(shifts2, p.shifts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1056,8 +1265,9 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         ctx->stats.init_ms = elapsed(ctx->ev[0], ctx->ev[1]);
         ctx->stats.sweeps_ms = elapsed(ctx->ev[1], ctx->ev[2]);
         ctx->stats.final_fit_ms = elapsed(ctx->ev[2], ctx->ev[3]);
-        ctx->stats.fit_gram = fits[done];
+        ctx->stats.fit_gram = fits[total];
         ctx->stats.sweeps = done;
+        ctx->stats.refine_sweeps = p.refine;
         ctx->stats.chol_shifts = shifts2[0];
         ctx->stats.orth_second_passes = shifts2[1];
         ctx->stats.workspace_bytes = ctx->ws_bytes;
@@ -1127,6 +1337,105 @@ tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int6
         });
         gram(r, in, dims, ndim, mode);
         TK_HIP(f64_to_f32(p.S64, out, sdim * sdim, r.st));
+    });
+}
+
+tucker_status tucker_quantize(tucker_ctx* ctx, const float* x, int64_t rows, int64_t L, tucker_precision precision,
+                              float* out, float* scales) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!x || !out || rows < 0 || L < 1 || L > 256 || precision < TUCKER_BF16 || precision > TUCKER_FP8_E4M3 ||
+        (precision == TUCKER_FP8_E4M3 && !scales))
+        return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        const int64_t n = rows * L;
+        void* q = nullptr;
+        float* part = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            q = a.take<uint16_t>(n);
+            part = a.take<float>(kLpScaleBlocks * L);
+        });
+        const float* sc = nullptr;
+        if (precision == TUCKER_FP8_E4M3) {
+            TK_HIP(slice_scales(x, rows, (int)L, part, kLpScaleBlocks, scales, r.st));
+            sc = scales;
+        }
+        TK_HIP(to_lowp(x, n, (int)precision, (int)L, sc, q, r.st));
+        TK_HIP(from_lowp(q, n, (int)precision, (int)L, sc, out, r.st));
+    });
+}
+
+tucker_status tucker_ttm_lowp(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims, int mode,
+                              const float* U, int64_t rnew, tucker_precision precision, float* out) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!in || !dims || !U || !out || ndim < 1 || ndim > TUCKER_MAX_ORDER || mode < 0 || mode >= ndim || rnew < 1 ||
+        precision < TUCKER_BF16 || precision > TUCKER_FP8_E4M3)
+        return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (dims[n] < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        const int64_t A = prod(dims, 0, mode), K = dims[mode], B = prod(dims, mode + 1, ndim);
+        const int64_t Last = dims[ndim - 1], n = A * K * B, Kp = (K + 7) / 8 * 8;
+        void *xq = nullptr, *ut = nullptr;
+        float *xs = nullptr, *us = nullptr, *part = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            xq = a.take<uint16_t>(n);
+            ut = a.take<uint16_t>(rnew * Kp);
+            xs = a.take<float>(Last);
+            us = a.take<float>(rnew);
+            part = a.take<float>(kLpScaleBlocks * Last);
+        });
+        const bool f8 = precision == TUCKER_FP8_E4M3;
+        if (f8 && Last > 256) throw Fail{TUCKER_ERR_UNSUPPORTED, "FP8 slice scales need a last mode <= 256"};
+        if (f8) TK_HIP(slice_scales(in, n / Last, (int)Last, part, kLpScaleBlocks, xs, r.st));
+        TK_HIP(to_lowp(in, n, (int)precision, (int)Last, f8 ? xs : nullptr, xq, r.st));
+        TK_HIP(factor_lowp(U, K, rnew, Kp, (int)precision, f8 ? us : nullptr, ut, r.st));
+        // out[a][r][b] = sum_k Ut[r][k] X[a][k][b]: M = r, N = (a, b), B operand rows k
+        LpGemmArgs g{};
+        g.a = plain(ut, Kp);
+        g.b = (B == 1) ? folded(xq, 1, 1, K) : folded(xq, B, B, K * B);
+        g.c = (B == 1) ? folded(out, 1, 1, rnew) : folded(out, B, B, rnew * B);
+        g.M = rnew;
+        g.N = A * B;
+        g.K = K;
+        g.alpha = 1.0;
+        g.sa = f8 ? us : nullptr;
+        g.sb = f8 ? xs : nullptr;
+        g.sb_mod = Last;
+        if (f8 && B % Last != 0 && B != 1)
+            throw Fail{TUCKER_ERR_UNSUPPORTED, "FP8 product needs the scaled mode among the kept columns"};
+        if (f8 && B == 1) throw Fail{TUCKER_ERR_UNSUPPORTED, "FP8 product over the scaled (last) mode"};
+        TK_HIP(gemm_lp(g, (int)precision, KM, LP_F32OUT, r.st));
+    });
+}
+
+tucker_status tucker_gram_lowp(tucker_ctx* ctx, const float* in, int ndim, const int64_t* dims, int mode,
+                               tucker_precision precision, float* out) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    if (!in || !dims || !out || ndim < 1 || ndim > TUCKER_MAX_ORDER || mode < 0 || mode >= ndim ||
+        (precision != TUCKER_BF16 && precision != TUCKER_FP16))
+        return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (dims[n] < 1) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        Plan& p = r.p;
+        const int64_t A = prod(dims, 0, mode), sd = dims[mode], B = prod(dims, mode + 1, ndim);
+        const int64_t n = A * sd * B, K = A * B;
+        void* xq = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            xq = a.take<uint16_t>(n);
+            p.S64 = a.take<double>(sd * sd);
+            p.Pf_elems = lp_gram_partials(sd, K);
+            p.Pf = a.take<float>(p.Pf_elems);
+        });
+        p.ip = (int)precision;
+        TK_HIP(to_lowp(in, n, (int)precision, 1, nullptr, xq, r.st));
+        // rows i of the mode, columns (a, b) with b contiguous
+        const Desc y = (B == 1) ? folded(xq, 1, 1, sd) : folded(xq, B, B, sd * B);
+        lp_gram(r, y, sd, K, -1);
+        TK_HIP(f64_to_f32(p.S64, out, sd * sd, r.st));
     });
 }
 

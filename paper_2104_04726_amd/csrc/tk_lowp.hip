@@ -514,8 +514,10 @@ hipError_t gemm_lp(const LpGemmArgs& gin, int prec, Orient ob, int outp, hipStre
         return ob == KM ? by_out<LP_F16, KM>(g, outp, vec, s) : by_out<LP_F16, MK>(g, outp, vec, s);
     }
     if (prec == LP_FP8) {
-        if (ob != KM || outp != LP_BF16) return hipErrorInvalidValue;   // FP8 only for the full-tensor product
-        return launch_lp<LP_FP8, KM, LP_BF16>(g, vec, s);
+        if (ob != KM) return hipErrorInvalidValue;   // FP8 only for the products over a tensor
+        if (outp == LP_BF16) return launch_lp<LP_FP8, KM, LP_BF16>(g, vec, s);
+        if (outp == LP_F32OUT) return launch_lp<LP_FP8, KM, LP_F32OUT>(g, vec, s);
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
