@@ -33,32 +33,49 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense matrix peaks
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0}   # MI355X dense
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stage_work(dims, ranks):
+def stage_work(dims, ranks, precision="fp32"):
     """Algorithmic work of one launch of each single-kernel stage of a tree sweep.
 
-    Returns {stage: (kind, amount)} with kind 'hbm' (bytes), 'f32' or 'f64' (MFMA flops in that
-    type).  Bytes are the reads of the input and writes of the output once; flops are 2 * MACs
-    (the Gram counts the lower triangle it computes: s^2 K).  The Grams run on the FP64 matrix
-    cores (FP32 data, exact products, FP64 accumulation); the mode products on the FP32 ones.
+    Returns {stage: (kind, amount)} with kind 'hbm' (bytes) or a matrix-core type 'f32', 'f64',
+    'bf16', 'f16', 'fp8' (flops).  Bytes are the reads of the input and writes of the output
+    once; flops are 2 * MACs (the Gram counts the lower triangle it computes: s^2 K).  In FP32
+    the Grams run on the FP64 matrix cores (FP32 data, exact products, FP64 accumulation) and the
+    mode products on the FP32 ones; in reduced precision every contraction runs in the 16-bit
+    type (FP8: the two products over X in FP8, the rest in BF16) and the two full-tensor passes
+    are priced by their bytes (X in the storage type, outputs in the 16-bit type, T34 rows padded
+    to a multiple of 8).
     """
     s0, s1, s2, s3 = dims
     r0, r1, r2, r3 = ranks
     r23, L = r2 * r3, s2 * s3
+    if precision == "fp32":
+        return {
+            "pass_a": ("hbm", 4 * (s0 * s1 * L + s0 * s1 * r23)),
+            "ttm_y1": ("f32", 2 * r1 * s1 * (s0 * r23)),
+            "gram_1": ("f64", s0 * s0 * (r1 * r23)),
+            "ttm_y2": ("f32", 2 * r0 * s0 * (s1 * r23)),
+            "gram_2": ("f64", s1 * s1 * (r0 * r23)),
+            "pass_c1": ("f32", 2 * r0 * s0 * (s1 * L)),
+            "ttm_c2": ("f32", 2 * r1 * s1 * (r0 * L)),
+        }
+    ex = 1 if precision == "fp8" else 2
+    it = "bf16" if precision in ("bf16", "fp8") else "f16"
+    r23p = (r23 + 7) // 8 * 8
     return {
-        "pass_a": ("hbm", 4 * (s0 * s1 * L + s0 * s1 * r23)),
-        "ttm_y1": ("f32", 2 * r1 * s1 * (s0 * r23)),
-        "gram_1": ("f64", s0 * s0 * (r1 * r23)),
-        "ttm_y2": ("f32", 2 * r0 * s0 * (s1 * r23)),
-        "gram_2": ("f64", s1 * s1 * (r0 * r23)),
-        "pass_c1": ("f32", 2 * r0 * s0 * (s1 * L)),
-        "ttm_c2": ("f32", 2 * r1 * s1 * (r0 * L)),
+        "pass_a": ("hbm", ex * s0 * s1 * L + 2 * s0 * s1 * r23p),
+        "ttm_y1": (it, 2 * r1 * s1 * (s0 * r23p)),
+        "gram_1": (it, s0 * s0 * (r1 * r23p)),
+        "ttm_y2": (it, 2 * r0 * s0 * (s1 * r23p)),
+        "gram_2": (it, s1 * s1 * (r0 * r23p)),
+        "pass_c1": ("hbm", ex * s0 * s1 * L + 2 * r0 * s1 * L),
+        "ttm_c2": (it, 2 * r1 * s1 * (r0 * L)),
     }
 
 
@@ -140,6 +157,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--init-iters", type=int, default=20,
+                    help="cold-start orthogonal-iteration steps of the T-HOSVD start")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -166,7 +185,7 @@ def main():
     x = torch.from_numpy(x32).to("cuda:0")
     torch.cuda.synchronize()
 
-    ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1)
+    ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
@@ -190,7 +209,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} sweeps/s, fit {r.fit:.8f}, "
         f"second CholeskyQR passes {r.stats.get('orth_second_passes')}")
 
-    work = stage_work(dims, ranks)
+    work = stage_work(dims, ranks, args.precision)
     stages = {}
     for name, (ms, calls) in sorted(stage_tot.items()):
         per = ms / calls
@@ -201,7 +220,7 @@ def main():
     dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
     kind, amount = work[dominant]
     roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
-    traffic = measured_traffic(dominant)
+    traffic = measured_traffic(dominant) if args.precision == "fp32" else None
     roof.update({"kernel": dominant, "traffic": traffic["total_bytes"] if traffic else None,
                  "traffic_unit": "bytes per launch", "traffic_detail": traffic,
                  "per_launch": f"{amount / 1e9:.3f} {'GB' if kind == 'hbm' else 'GFLOP'}"})

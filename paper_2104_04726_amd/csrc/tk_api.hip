@@ -97,6 +97,7 @@ struct Plan {
     // reduced-precision sweeps (tree shapes): storage type of X (prec) and of the intermediates (ip)
     int prec = 0, ip = 0;
     int64_t R23p = 0;        // R3 R4 rounded up to 8: padded fibre length of T34 / Y0 / Y1
+    int64_t Lp = 0;          // s3 s4 rounded up to 8: padded fibre length of T1 (zero padding)
     void *Xlp = nullptr, *T34lp = nullptr, *Y0lp = nullptr, *Y1lp = nullptr, *T1lp = nullptr;
     void *U1t = nullptr, *U2t = nullptr, *U1t8 = nullptr;   // transposed factor copies (rows padded to 8)
     float *xscale = nullptr, *u1scale = nullptr, *spart = nullptr;
@@ -229,7 +230,8 @@ void build_plan(Plan& p, Arena& a) {
             p.T34lp = a.take<uint16_t>(s0 * s1 * p.R23p);
             p.Y0lp = a.take<uint16_t>(s0 * R1 * p.R23p);
             p.Y1lp = a.take<uint16_t>(R0 * s1 * p.R23p);
-            p.T1lp = a.take<uint16_t>(R0 * s1 * L);
+            p.Lp = (L + 7) / 8 * 8;
+            p.T1lp = a.take<uint16_t>(R0 * s1 * p.Lp);
             p.U1t = a.take<uint16_t>(R0 * s0p);
             p.U2t = a.take<uint16_t>(R1 * s1p);
             p.U1t8 = a.take<uint8_t>(R0 * s0p);
@@ -593,12 +595,23 @@ void core_norm_and_fit(Run& r, double* fit_slot) {
 // ------------------------------------------------------------------ T-HOSVD initialisation
 void thosvd(Run& r) {
     Plan& p = r.p;
+    // tree shapes: the Grams of the two small trailing modes come from the fibre Gram of X (one
+    // coalesced pass over X), F = sum_(h,w) x_(h,w) x_(h,w)^T over the (s3 s4)-long fibres
+    bool have_f = false;
     for (int n = 0; n < p.N; ++n) {
         if (p.kind[n] == FIXED) {
             identity_factor(r, n);
             continue;
         }
-        gram(r, r.X, p.s, p.N, n);
+        if (p.tree && n >= 2) {
+            if (!have_f) {
+                TK_HIP(fibre_gram(r.X, p.s[0] * p.s[1], (int)(p.s[2] * p.s[3]), p.Fpart, kFibreGramBlocks, p.F, r.st));
+                have_f = true;
+            }
+            TK_HIP(pair_mode_gram(p.F, (int)p.s[2], (int)p.s[3], nullptr, 0, n == 2 ? 3 : 4, p.S64, r.st));
+        } else {
+            gram(r, r.X, p.s, p.N, n);
+        }
         update_factor(r, n, true);
     }
 }
@@ -684,6 +697,8 @@ void lp_convert_x(Run& r) {
         scale = p.xscale;
     }
     TK_HIP(to_lowp(r.X, Xn, p.prec, (int)L, scale, p.Xlp, r.st));
+    // T1 rows are padded from L to Lp; the padding is never written and must read as zero
+    if (p.Lp != L) TK_HIP(fill_zero(p.T1lp, p.R[0] * p.s[1] * p.Lp * (int64_t)sizeof(uint16_t), r.st));
 }
 
 // transposed reduced-precision copy of factor n: Ut (R x round8(s)), k contiguous
@@ -695,8 +710,9 @@ void lp_factor(Run& r, int n, int prec, void* Ut, float* scale) {
 
 // mode product out = B x U^T on the matrix cores: A = Ut (M = R rows, K = s), B an n-contiguous view
 void lp_ttm(Run& r, int prec, const void* Ut, int64_t R, int64_t K, Desc b, int64_t N, Desc c, int outp,
-            const float* sa = nullptr, const float* sb = nullptr, int64_t sb_mod = 0) {
+            const float* sa = nullptr, const float* sb = nullptr, int64_t sb_mod = 0, int64_t c_valid = 0) {
     LpGemmArgs g{};
+    g.c_valid = c_valid;
     g.a = plain(Ut, (K + 7) / 8 * 8);
     g.b = b;
     g.c = c;
@@ -770,22 +786,23 @@ void sweep_tree_lp(Run& r) {
         StageTimer t(r, TUCKER_STAGE_OI_2);
         update_factor(r, 1, false);
     }
-    // T1 = X x_1 U1^T (second pass over X), T12 = T1 x_2 U2^T in FP32
+    // T1 = X x_1 U1^T (second pass over X, rows of T1 padded to Lp), T12 = T1 x_2 U2^T in FP32
+    const int64_t Lp = p.Lp;
     {
         StageTimer t(r, TUCKER_STAGE_PASS_C1);
+        const Desc t1 = folded(p.T1lp, s1 * Lp, L, Lp);
         if (p.prec == TUCKER_FP8_E4M3) {
             lp_factor(r, 0, TUCKER_FP8_E4M3, p.U1t8, p.u1scale);
-            lp_ttm(r, TUCKER_FP8_E4M3, p.U1t8, R0, s0, plain(p.Xlp, s1 * L), s1 * L, plain(p.T1lp, s1 * L), ip,
-                   p.u1scale, p.xscale, L);
+            lp_ttm(r, TUCKER_FP8_E4M3, p.U1t8, R0, s0, plain(p.Xlp, s1 * L), s1 * L, t1, ip, p.u1scale, p.xscale, L);
         } else {
-            lp_ttm(r, p.prec, p.U1t, R0, s0, plain(p.Xlp, s1 * L), s1 * L, plain(p.T1lp, s1 * L), ip);
+            lp_ttm(r, p.prec, p.U1t, R0, s0, plain(p.Xlp, s1 * L), s1 * L, t1, ip);
         }
     }
     {
         StageTimer t(r, TUCKER_STAGE_TTM_C2);
         lp_factor(r, 1, ip, p.U2t, nullptr);
-        lp_ttm(r, ip, p.U2t, R1, s1, folded(p.T1lp, L, L, s1 * L), R0 * L, folded(p.T12, L, L, R1 * L),
-               LP_F32OUT);
+        lp_ttm(r, ip, p.U2t, R1, s1, folded(p.T1lp, Lp, Lp, s1 * Lp), R0 * Lp, folded(p.T12, L, Lp, R1 * L),
+               LP_F32OUT, nullptr, nullptr, 0, L);
     }
     // modes 3 and 4 and the core exactly as in the FP32 sweep
     if (p.kind[2] != FIXED || p.kind[3] != FIXED) {

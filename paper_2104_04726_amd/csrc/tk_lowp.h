@@ -17,6 +17,7 @@ struct LpGemmArgs {
     const float* sa;      // per-row output scale (nullable)
     const float* sb;      // per-column output scale, index n % sb_mod (nullable)
     int64_t sb_mod;
+    int64_t c_valid;      // > 0: columns n with n % c.seg >= c_valid are padding and not written
 };
 
 // C = alpha diag(sa) (A B) diag(sb): A k-contiguous (desc rows m, columns k); B n-contiguous

@@ -302,6 +302,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(LpGemmArgs g) {
     for (int j = 0; j < 4; ++j) {
         const int64_t n = n0 + wbn + j * 16 + fr;
         if (n >= g.N) continue;
+        if (g.c_valid > 0 && (n % g.c.seg) >= g.c_valid) continue;   // padding columns of a folded output
         const int64_t co = coloff(g.c, n);
         const float cs = (float)g.alpha * (g.sb ? g.sb[n % g.sb_mod] : 1.0f);
 #pragma unroll
@@ -426,6 +427,146 @@ __global__ __launch_bounds__(256) void from_lp_kernel(const typename Codec<P>::S
 }
 
 // ---------------------------------------------------------------------------- two-mode pass
+// Fixed-shape version of the pass below (P x Q fibres, ranks R3, R4, output rows of LDO): the
+// chunk of 256 fibres is read with 16-byte coalesced loads prefetched one chunk ahead, decoded
+// into LDS, mapped one fibre per thread with U3 in registers and U4 in LDS, and written back
+// with 16-byte stores.
+template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO>
+__global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S* __restrict__ in, int64_t A,
+                                                     const float* __restrict__ U3, const float* __restrict__ U4,
+                                                     const float* __restrict__ scale, uint16_t* __restrict__ out) {
+    typedef typename Codec<P>::S S;
+    constexpr int ES = (int)sizeof(S);
+    constexpr int LIN = PP * QQ, SIN = LIN | 1;
+    constexpr int FPB = 256;
+    constexpr int EPV = 16 / ES;                        // elements per 16-byte vector
+    constexpr int NV_IN = FPB * LIN / EPV;              // vectors per full chunk
+    constexpr int VPT = (NV_IN + 255) / 256;
+    constexpr int NV_OUT = FPB * LDO * 2 / 16;
+    static_assert((FPB * LIN) % EPV == 0 && (FPB * LDO * 2) % 16 == 0, "chunk not a whole number of vectors");
+    __shared__ float fin[FPB * SIN];
+    __shared__ __attribute__((aligned(16))) uint16_t fout[FPB * LDO];
+    __shared__ float u4s[QQ * R4];
+    __shared__ float sc[LIN];
+    for (int i = threadIdx.x; i < QQ * R4; i += 256) u4s[i] = U4[i];
+    for (int i = threadIdx.x; i < LIN; i += 256) sc[i] = scale ? scale[i] : 1.0f;
+    float u3[PP * R3];
+#pragma unroll
+    for (int i = 0; i < PP * R3; ++i) u3[i] = U3[i];
+
+    const int64_t nchunks = (A + FPB - 1) / FPB;
+    const int64_t full = A / FPB;
+    uint4 pre[VPT];
+    auto prefetch = [&](int64_t ch) {
+        if (ch < full) {
+            const uint4* src = (const uint4*)(in + ch * FPB * LIN);
+#pragma unroll
+            for (int u = 0; u < VPT; ++u) {
+                const int i = threadIdx.x + 256 * u;
+                if (i < NV_IN) pre[u] = src[i];
+            }
+        }
+    };
+    int64_t ch = blockIdx.x;
+    prefetch(ch);
+    for (; ch < nchunks; ch += gridDim.x) {
+        const int64_t f0 = ch * FPB;
+        const int nf = (int)((A - f0) < FPB ? (A - f0) : FPB);
+        __syncthreads();
+        if (ch < full) {
+#pragma unroll
+            for (int u = 0; u < VPT; ++u) {
+                const int i = threadIdx.x + 256 * u;
+                if (i < NV_IN) {
+                    const S* e = (const S*)&pre[u];
+#pragma unroll
+                    for (int j = 0; j < EPV; ++j) {
+                        const int g = EPV * i + j;
+                        const int l = g % LIN;
+                        fin[(g / LIN) * SIN + l] = Codec<P>::dec(e[j]) * sc[l];
+                    }
+                }
+            }
+        } else {
+            const S* src = in + f0 * LIN;
+            for (int g = threadIdx.x; g < nf * LIN; g += 256) {
+                const int l = g % LIN;
+                fin[(g / LIN) * SIN + l] = Codec<P>::dec(src[g]) * sc[l];
+            }
+        }
+        __syncthreads();
+        prefetch(ch + gridDim.x);
+        const int f = threadIdx.x;
+        if (f < nf) {
+            const float* x = fin + f * SIN;
+            float tmp[PP][R4];
+#pragma unroll
+            for (int c = 0; c < PP; ++c)
+#pragma unroll
+                for (int t = 0; t < R4; ++t) tmp[c][t] = 0.f;
+#pragma unroll
+            for (int i = 0; i < QQ; ++i) {
+                float xc[PP];
+#pragma unroll
+                for (int c = 0; c < PP; ++c) xc[c] = x[c * QQ + i];
+#pragma unroll
+                for (int t = 0; t < R4; ++t) {
+                    const float w = u4s[i * R4 + t];
+#pragma unroll
+                    for (int c = 0; c < PP; ++c) tmp[c][t] = fmaf(xc[c], w, tmp[c][t]);
+                }
+            }
+            uint16_t* y = fout + f * LDO;
+#pragma unroll
+            for (int r = 0; r < R3; ++r)
+#pragma unroll
+                for (int t = 0; t < R4; ++t) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int c = 0; c < PP; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                    y[r * R4 + t] = (OUTP == LP_BF16) ? enc_bf16(acc) : enc_f16(acc);
+                }
+#pragma unroll
+            for (int o = R3 * R4; o < LDO; ++o) y[o] = 0;
+        }
+        __syncthreads();
+        if (nf == FPB) {
+            uint4* dst = (uint4*)(out + f0 * LDO);
+            const uint4* s4 = (const uint4*)fout;
+            for (int i = threadIdx.x; i < NV_OUT; i += 256) dst[i] = s4[i];
+        } else {
+            uint16_t* dst = out + f0 * LDO;
+            for (int g = threadIdx.x; g < nf * LDO; g += 256) dst[g] = fout[g];
+        }
+    }
+}
+
+template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO>
+bool try_pair_lp(const void* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
+                 const float* scale, int ldo, void* out, hipStream_t s, hipError_t* err) {
+    if (p != PP || q != QQ || r3 != R3 || r4 != R4 || ldo != LDO) return false;
+    if ((((uintptr_t)in) & 15) != 0 || (((uintptr_t)out) & 15) != 0) return false;
+    const int64_t nchunks = (A + 255) / 256;
+    const unsigned grid = (unsigned)(nchunks < 1024 ? nchunks : 1024);
+    hipLaunchKernelGGL((pair_lp_fixed<P, OUTP, PP, QQ, R3, R4, LDO>), dim3(grid), dim3(256), 0, s,
+                       (const typename Codec<P>::S*)in, A, U3, U4, scale, (uint16_t*)out);
+    *err = hipGetLastError();
+    return true;
+}
+
+template <int P, int OUTP>
+bool pair_lp_any_fixed(const void* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
+                       const float* scale, int ldo, void* out, hipStream_t s, hipError_t* err) {
+    // the image-stack fibre shapes: 3 colour channels x 2E images, R4 = 2E - 1 or the reduced ranks
+    return try_pair_lp<P, OUTP, 3, 14, 3, 8, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 10, 3, 6, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 6, 3, 4, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 6, 3, 5, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 10, 3, 9, 32>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 14, 3, 13, 40>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err);
+}
+
+// ---------------------------------------------------------------------------- two-mode pass (generic)
 // T34[a][r][t] (row stride ldo >= R3 R4, padding written as zero) = sum_{c,i} U3[c][r] U4[i][t] x[a][c][i]
 // where x[a][c][i] = dec(in[a][c][i]) * (scale ? scale[c q + i] : 1).  One thread per fibre; the
 // fibres of a 256-fibre chunk are staged through LDS with coalesced loads; output in OUTP.
@@ -595,6 +736,17 @@ hipError_t pair_lowp(const void* in, int64_t A, int p, int q, const float* U3, i
     if (p < 1 || p > 4 || q < 1 || q > 16 || R3 > p || R4 > q || ldo < R3 * R4 || ldo > 64) return hipErrorInvalidValue;
     if (outp != LP_BF16 && outp != LP_F16) return hipErrorInvalidValue;
     if (A == 0) return hipSuccess;
+    {
+        hipError_t e = hipSuccess;
+        bool done = false;
+        if (prec == LP_BF16 && outp == LP_BF16)
+            done = pair_lp_any_fixed<LP_BF16, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+        else if (prec == LP_F16 && outp == LP_F16)
+            done = pair_lp_any_fixed<LP_F16, LP_F16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+        else if (prec == LP_FP8 && outp == LP_BF16)
+            done = pair_lp_any_fixed<LP_FP8, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+        if (done) return e;
+    }
     const int64_t nchunks = (A + 255) / 256;
     const unsigned grid = (unsigned)(nchunks < 2048 ? nchunks : 2048);
 #define TK_PAIR(PP, OO)                                                                                          \

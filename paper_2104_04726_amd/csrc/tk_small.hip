@@ -426,8 +426,18 @@ __global__ __launch_bounds__(256) void fibre_gram_reduce(const double* __restric
         while ((i + 1) * (i + 2) / 2 <= idx) ++i;
         while (i * (i + 1) / 2 > idx) --i;
         const int j = idx - i * (i + 1) / 2;
+        // eight loads in flight, summed in block order (same result as a plain loop)
         double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * L * L + i * L + j];
+        const int64_t st = (int64_t)L * L, off = (int64_t)i * L + j;
+        int b = 0;
+        for (; b + 8 <= nblocks; b += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(b + u) * st + off];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; b < nblocks; ++b) s += partial[(int64_t)b * st + off];
         F[i * L + j] = s;
         F[j * L + i] = s;
     }
@@ -527,8 +537,18 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const float* __restric
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / n, j = e % n;
         const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
+        // loads issued four at a time, summed in split order (same result as a plain loop)
         double s = 0.0;
-        for (int z = 0; z < nsplit; ++z) s += (double)P[z * zstride + src];
+        int z = 0;
+        for (; z + 4 <= nsplit; z += 4) {
+            const float a0 = P[(int64_t)z * zstride + src], a1 = P[(int64_t)(z + 1) * zstride + src];
+            const float a2 = P[(int64_t)(z + 2) * zstride + src], a3 = P[(int64_t)(z + 3) * zstride + src];
+            s += (double)a0;
+            s += (double)a1;
+            s += (double)a2;
+            s += (double)a3;
+        }
+        for (; z < nsplit; ++z) s += (double)P[(int64_t)z * zstride + src];
         if (S32) S32[e] = (float)s;
         if (S64) S64[e] = s;
     }
@@ -543,7 +563,16 @@ __global__ __launch_bounds__(256) void gram_reduce64_kernel(const double* __rest
         const int64_t i = e / n, j = e % n;
         const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
         double s = 0.0;
-        for (int z = 0; z < nsplit; ++z) s += P[z * zstride + src];
+        int z = 0;
+        for (; z + 4 <= nsplit; z += 4) {
+            const double a0 = P[(int64_t)z * zstride + src], a1 = P[(int64_t)(z + 1) * zstride + src];
+            const double a2 = P[(int64_t)(z + 2) * zstride + src], a3 = P[(int64_t)(z + 3) * zstride + src];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; z < nsplit; ++z) s += P[(int64_t)z * zstride + src];
         S64[e] = s;
     }
 }
