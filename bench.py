@@ -136,6 +136,123 @@ def measured_traffic(stage):
     return None
 
 
+def _gen_stack(args):
+    from synth import make_stereo_stack
+    H, W, seed = args
+    return make_stereo_stack(H, W, 7, "ycbcr", seed)
+
+
+def serve(args):
+    """Served execution: Poisson-arriving requests of mixed resolution and exposure count (the
+    serving configuration), BF16 sweeps + 1 FP32 refinement, admitted by HBM budget with several
+    requests on the GPU at once.  Tensors: one seeded E = 7 stack per resolution; a request with
+    E = 3 or 5 exposures uses the middle exposures of each view, which is exactly the stack the
+    generator makes for that E (same radiance field and exposure scale)."""
+    import concurrent.futures as cf
+    import threading
+    import numpy as np
+    import torch
+    import paper_2104_04726_amd as tk
+    from synth import serving_requests
+
+    reqs = serving_requests(args.requests, 0.025, 3)
+    sizes = sorted({(q["H"], q["W"]) for q in reqs})
+    log(f"generating {len(sizes)} base stacks")
+    with cf.ProcessPoolExecutor(max_workers=min(4, len(sizes))) as ex:
+        base = dict(zip(sizes, ex.map(_gen_stack, [(H, W, 3000 + i) for i, (H, W) in enumerate(sizes)])))
+    cells = {}
+    for (H, W), x7 in base.items():
+        for E in (3, 5, 7):
+            lo = (7 - E) // 2
+            x = np.concatenate([x7[..., v * 7 + lo: v * 7 + lo + E] for v in range(2)], axis=-1)
+            cells[(H, W, E)] = torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
+    del base
+    iters = 10
+
+    def run(srv, items, open_loop):
+        t0 = time.perf_counter()
+        ids = [None] * len(items)
+
+        def submitter():
+            for k, q in enumerate(items):
+                if open_loop:
+                    d = q["t_arrive"] - (time.perf_counter() - t0)
+                    if d > 0:
+                        time.sleep(d)
+                ids[k] = srv.submit(cells[(q["H"], q["W"], q["E"])], q["ranks"], iters, precision=args.serve_precision,
+                                    refine_sweeps=1 if args.serve_precision != "fp32" else 0, tag=k)
+        th = threading.Thread(target=submitter)
+        th.start()
+        out = []
+        for k in range(len(items)):
+            while ids[k] is None:
+                time.sleep(0.0005)
+            out.append(srv.wait(ids[k]))
+        th.join()
+        wall = time.perf_counter() - t0
+        return out, wall
+
+    def summary(res, wall):
+        lat = np.array([r.latency for r in res]) * 1e3
+        bad = [r for r in res if r.status != 0]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed: {bad[0].error}")
+        span = max(r.t_finish for r in res) - min(r.t_submit for r in res)
+        return {"requests": len(res), "decomp_per_s": round(len(res) / span, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
+                "wall_s": round(wall, 3)}
+
+    # warm-up (kernels loaded, memory pool primed) on one request of every size
+    with tk.Server(0, slots=args.slots) as srv:
+        warm = [dict(H=H, W=W, E=7, ranks=(H // 4, W // 4, 3, 13), t_arrive=0.0) for (H, W) in sizes]
+        run(srv, warm, open_loop=False)
+        log(f"open loop: {len(reqs)} requests, Poisson 40/s, {args.slots} slots")
+        res_open, wall_open = run(srv, reqs, open_loop=True)
+        open_sum = summary(res_open, wall_open)
+        log(f"  {open_sum}")
+        nsat = min(len(reqs), args.saturated)
+        log(f"saturated: {nsat} requests submitted at once")
+        res_sat, wall_sat = run(srv, reqs[:nsat], open_loop=False)
+        sat_sum = summary(res_sat, wall_sat)
+        log(f"  {sat_sum}")
+        st = srv.stats()
+    # baseline: the same requests one after another in plain FP32 (10 sweeps), on a stratified
+    # sample of one request per (resolution, exposures) cell
+    ctx = tk.Context(0)
+    times = []
+    for (H, W, E), xh in sorted(cells.items()):
+        xd = xh.cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.decompose(xd, (H // 4, W // 4, 3, 2 * E - 1), iters)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        del xd
+    ctx.close()
+    seq_rate = 1.0 / float(np.mean(times))
+    out = {
+        "metric": "served decompositions/s (p50/p99 latency)",
+        "value": open_sum["decomp_per_s"],
+        "unit": "decompositions/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": args.serve_precision,
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(reqs)} Poisson requests (mean 40/s), 640x480..2560x1440 x 3 x 2E, "
+                               f"E in 3/5/7, ranks (H/4, W/4, 3, 2E-1), {iters} {args.serve_precision} sweeps"
+                               + (" + 1 FP32 refinement" if args.serve_precision != "fp32" else ""),
+                   "slots": args.slots, "budget_bytes": st["budget_bytes"],
+                   "peak_admitted_bytes": st["peak_admitted_bytes"], "peak_running": st["peak_running"]},
+        "open_loop": open_sum,
+        "saturated": sat_sum,
+        "sequential_fp32_baseline": {"decomp_per_s": round(seq_rate, 3),
+                                     "sample": f"{len(times)} requests, one per (resolution, E) cell, plain FP32, "
+                                               f"{iters} sweeps, one at a time"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     """A plain elementwise kernel that reads and writes nbytes each (y = -x, FP32): what the HBM
     byte counters report for it calibrates them against a known algorithmic traffic."""
@@ -161,11 +278,19 @@ def main():
                     help="cold-start orthogonal-iteration steps of the T-HOSVD start")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
+    ap.add_argument("--serve", action="store_true", help="run the served-execution benchmark instead")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--saturated", type=int, default=128)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp16", "fp8"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.serve:
+        serve(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the decomposition is not "

@@ -45,7 +45,8 @@ typedef enum {
     TUCKER_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or exceeds hbm_budget_bytes */
     TUCKER_ERR_DEVICE = 3,        /* no usable GPU, or a HIP runtime error                */
     TUCKER_ERR_NUMERICAL = 4,     /* non-finite input norm, or an unrecoverable breakdown */
-    TUCKER_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement        */
+    TUCKER_ERR_UNSUPPORTED = 5,   /* a valid request this build does not implement        */
+    TUCKER_ERR_TIMEOUT = 6        /* tucker_server_wait: the request has not finished yet */
 } tucker_status;
 
 /* Operand precision of the TTM and Gram contractions of the sweeps (the precision variants of the
@@ -229,6 +230,80 @@ tucker_status tucker_sym_eig(tucker_ctx* ctx, const float* S, int64_t n, int64_t
 /* Sum of squares of n floats accumulated in FP64 (two-stage, deterministic).
  * x device; result host.  Synchronises. */
 tucker_status tucker_sumsq(tucker_ctx* ctx, const float* x, int64_t n, double* result);
+
+/* ---- Served execution: a request loop with admission by HBM budget ----
+ *
+ * Decompositions of many tensors (image stacks of different resolutions and exposure counts)
+ * arrive over time.  The server keeps `slots` decompositions on the GPU at once, each on its own
+ * stream with its own workspace, so their kernels overlap on the device; a request is admitted
+ * (strictly first come, first served) when a slot is free and its device footprint fits in what
+ * is left of hbm_budget_bytes.  Per request the server copies the host tensor to the device,
+ * runs the same decomposition as tucker_decompose_ex with the request's precision, copies core
+ * and factors back to the caller's host buffers and releases its device memory.  Every kernel's
+ * result depends only on its own inputs (fixed reduction orders), so a result is the same alone
+ * and in any mix of concurrent requests.
+ *
+ * Ownership: the caller owns host_tensor, host_core and host_factors[], which must stay valid
+ * until tucker_server_wait has returned that request's result.  The server owns all device
+ * memory it uses.  A server may be used from several host threads. */
+typedef struct tucker_server tucker_server;
+
+typedef struct {
+    int device;                  /* HIP device ordinal                                        */
+    int slots;                   /* decompositions on the GPU at once (>= 1)                  */
+    size_t hbm_budget_bytes;     /* cap on admitted footprints; 0 = 90% of free device memory */
+    int inner_iters;             /* as in tucker_options                                      */
+    int init_iters;
+    uint64_t seed;
+} tucker_server_options;
+
+typedef struct {
+    const float* host_tensor;    /* host, row-major dims[0] x ... (pinned memory copies fastest) */
+    int ndim;
+    int64_t dims[TUCKER_MAX_ORDER];
+    int64_t ranks[TUCKER_MAX_ORDER];
+    int max_iters;
+    double tol;
+    tucker_precision precision;
+    int refine_sweeps;           /* FP32 sweeps after reduced-precision ones                  */
+    uint64_t tag;                /* returned unchanged in the result                          */
+    float* host_core;            /* host, prod(ranks) floats, written by the server            */
+    float* host_factors[TUCKER_MAX_ORDER];   /* host, dims[n] * ranks[n] floats each          */
+} tucker_request;
+
+typedef struct {
+    tucker_status status;        /* of the decomposition                                      */
+    double fit;
+    int sweeps;
+    uint64_t tag;
+    int slot;                    /* slot that ran it                                          */
+    size_t footprint_bytes;      /* device memory charged against the budget                  */
+    double t_submit, t_admit, t_start, t_finish;   /* seconds since tucker_server_create      */
+    char error[160];             /* message when status != TUCKER_OK                          */
+} tucker_result;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    size_t budget_bytes;
+    size_t peak_admitted_bytes;  /* largest sum of admitted footprints seen                   */
+    int peak_running;            /* largest number of requests running at once               */
+} tucker_server_stats;
+
+/* Defaults: device 0, 4 slots, budget 0 (90% of free memory), inner_iters 1, init_iters 20. */
+void tucker_default_server_options(tucker_server_options* o);
+/* ERR_DEVICE without a usable GPU; ERR_INVALID_ARG for bad options. */
+tucker_status tucker_server_create(const tucker_server_options* opts, tucker_server** out);
+/* Validates the request as tucker_decompose does (INVALID_ARG, UNSUPPORTED for a reduced
+ * precision on a shape that has none) and enqueues it without blocking; a request whose
+ * footprint exceeds the whole budget is refused with ERR_OUT_OF_MEMORY.  *id identifies it. */
+tucker_status tucker_server_submit(tucker_server* srv, const tucker_request* req, uint64_t* id);
+/* Waits up to timeout_s seconds (< 0: forever) for request id; on TUCKER_OK *out holds its
+ * result (whose own status may be an error) and the id is retired.  ERR_TIMEOUT if it has not
+ * finished, ERR_INVALID_ARG for an unknown id. */
+tucker_status tucker_server_wait(tucker_server* srv, uint64_t id, double timeout_s, tucker_result* out);
+tucker_status tucker_server_get_stats(tucker_server* srv, tucker_server_stats* out);
+/* Finishes the running requests, fails the queued ones, frees everything. */
+tucker_status tucker_server_destroy(tucker_server* srv);
 
 /* ---- Diagnostics ---- */
 const char* tucker_status_string(tucker_status s);

@@ -24,7 +24,7 @@ from . import _lib
 from ._lib import FP32, BF16, FP16, FP8_E4M3  # noqa: F401
 
 __all__ = ["Context", "TuckerError", "Result", "decompose", "reconstruct", "default_context", "validate",
-           "workspace_size"]
+           "workspace_size", "Server", "Served"]
 
 _PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 
@@ -293,3 +293,119 @@ def decompose(x, ranks, max_iters: int = 10, tol: float = 0.0, init_factors=None
 
 def reconstruct(core, factors):
     return default_context(core.device.index or 0).reconstruct(core, factors)
+
+
+# ---------------------------------------------------------------------------------------------
+# Served execution
+# ---------------------------------------------------------------------------------------------
+
+@dataclass
+class Served:
+    """Result of one served request (host arrays)."""
+    status: int
+    error: str
+    fit: float
+    sweeps: int
+    tag: int
+    slot: int
+    footprint_bytes: int
+    t_submit: float
+    t_admit: float
+    t_start: float
+    t_finish: float
+    core: "object" = None           # numpy float32 (R_1, ..., R_N)
+    factors: List = field(default_factory=list)   # numpy float32 (s_n, R_n)
+
+    @property
+    def latency(self) -> float:
+        return self.t_finish - self.t_submit
+
+
+def _host_ptr(a):
+    """Address of a C-contiguous float32 host array (numpy array or CPU torch tensor)."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda or a.dtype != torch.float32 or not a.is_contiguous():
+                raise TuckerError(_lib.ERR_INVALID_ARG, "host tensor must be a contiguous float32 CPU tensor")
+            return a.data_ptr(), tuple(a.shape)
+    except ImportError:
+        pass
+    import numpy as np
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]):
+        raise TuckerError(_lib.ERR_INVALID_ARG, "host tensor must be a C-contiguous float32 numpy array")
+    return a.ctypes.data, tuple(a.shape)
+
+
+class Server:
+    """Request loop of the library (tucker_server_*): admission by HBM budget, `slots` requests
+    in flight on their own streams.  submit() copies nothing and returns at once; the host
+    tensor must stay alive until wait() returns its result."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0, inner_iters: int = 1,
+                 init_iters: int = 20, seed: int = 0x5EED):
+        o = _lib.ServerOptions()
+        _lib.lib().tucker_default_server_options(C.byref(o))
+        o.device, o.slots, o.hbm_budget_bytes = int(device), int(slots), int(hbm_budget_bytes)
+        o.inner_iters, o.init_iters, o.seed = int(inner_iters), int(init_iters), int(seed)
+        h = C.c_void_p()
+        _check(_lib.lib().tucker_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, x, ranks: Sequence[int], max_iters: int = 10, tol: float = 0.0, precision: str = "fp32",
+               refine_sweeps: int = 1, tag: int = 0) -> int:
+        import numpy as np
+        ptr, dims = _host_ptr(x)
+        n = len(dims)
+        ranks = [int(r) for r in ranks]
+        if len(ranks) != n or not 2 <= n <= _lib.MAX_ORDER:
+            raise TuckerError(_lib.ERR_INVALID_ARG, "ranks must match the tensor order (2..8)")
+        core = np.empty(ranks, dtype=np.float32)
+        factors = [np.empty((dims[i], ranks[i]), dtype=np.float32) for i in range(n)]
+        q = _lib.Request()
+        q.host_tensor = ptr
+        q.ndim = n
+        for i in range(n):
+            q.dims[i] = int(dims[i])
+            q.ranks[i] = ranks[i]
+            q.host_factors[i] = factors[i].ctypes.data
+        q.max_iters, q.tol = int(max_iters), float(tol)
+        q.precision, q.refine_sweeps, q.tag = _PRECISIONS[precision], int(refine_sweeps), int(tag)
+        q.host_core = core.ctypes.data
+        rid = C.c_uint64()
+        _check(_lib.lib().tucker_server_submit(self._h, C.byref(q), C.byref(rid)))
+        self._keep[rid.value] = (x, core, factors)
+        return rid.value
+
+    def wait(self, rid: int, timeout: Optional[float] = None) -> Served:
+        r = _lib.ServedResult()
+        _check(_lib.lib().tucker_server_wait(self._h, int(rid), -1.0 if timeout is None else float(timeout),
+                                             C.byref(r)))
+        _, core, factors = self._keep.pop(int(rid))
+        return Served(int(r.status), r.error.decode(errors="replace"), float(r.fit), int(r.sweeps), int(r.tag),
+                      int(r.slot), int(r.footprint_bytes), float(r.t_submit), float(r.t_admit), float(r.t_start),
+                      float(r.t_finish), core, factors)
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        _check(_lib.lib().tucker_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().tucker_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

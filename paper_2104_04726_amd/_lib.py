@@ -14,9 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TUCKER_LIB") or os.path.join(HERE, "libtucker_mi355x.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tucker.h")
 
-OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERICAL, ERR_UNSUPPORTED = range(6)
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERICAL, ERR_UNSUPPORTED, ERR_TIMEOUT = range(7)
 FP32, BF16, FP16, FP8_E4M3 = range(4)
-MAX_ORDER = 8
 
 
 class Options(C.Structure):
@@ -48,6 +47,63 @@ class Stats(C.Structure):
         ("workspace_bytes", C.c_size_t),
         ("stage_ms", C.c_double * 12),
         ("stage_calls", C.c_int * 12),
+    ]
+
+
+MAX_ORDER = 8
+
+
+class ServerOptions(C.Structure):
+    _fields_ = [
+        ("device", C.c_int),
+        ("slots", C.c_int),
+        ("hbm_budget_bytes", C.c_size_t),
+        ("inner_iters", C.c_int),
+        ("init_iters", C.c_int),
+        ("seed", C.c_uint64),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("host_tensor", C.c_void_p),
+        ("ndim", C.c_int),
+        ("dims", C.c_int64 * MAX_ORDER),
+        ("ranks", C.c_int64 * MAX_ORDER),
+        ("max_iters", C.c_int),
+        ("tol", C.c_double),
+        ("precision", C.c_int),
+        ("refine_sweeps", C.c_int),
+        ("tag", C.c_uint64),
+        ("host_core", C.c_void_p),
+        ("host_factors", C.c_void_p * MAX_ORDER),
+    ]
+
+
+class ServedResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int),
+        ("fit", C.c_double),
+        ("sweeps", C.c_int),
+        ("tag", C.c_uint64),
+        ("slot", C.c_int),
+        ("footprint_bytes", C.c_size_t),
+        ("t_submit", C.c_double),
+        ("t_admit", C.c_double),
+        ("t_start", C.c_double),
+        ("t_finish", C.c_double),
+        ("error", C.c_char * 160),
+    ]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64),
+        ("completed", C.c_int64),
+        ("failed", C.c_int64),
+        ("budget_bytes", C.c_size_t),
+        ("peak_admitted_bytes", C.c_size_t),
+        ("peak_running", C.c_int),
     ]
 
 
@@ -89,6 +145,16 @@ def _declare(lib):
     lib.tucker_quantize.argtypes = [v, v, C.c_int64, C.c_int64, C.c_int, v, v]
     lib.tucker_ttm_lowp.argtypes = [v, v, C.c_int, I64P, C.c_int, v, C.c_int64, C.c_int, v]
     lib.tucker_gram_lowp.argtypes = [v, v, C.c_int, I64P, C.c_int, C.c_int, v]
+    lib.tucker_default_server_options.argtypes = [C.POINTER(ServerOptions)]
+    lib.tucker_default_server_options.restype = None
+    lib.tucker_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(v)]
+    lib.tucker_server_submit.argtypes = [v, C.POINTER(Request), C.POINTER(C.c_uint64)]
+    lib.tucker_server_wait.argtypes = [v, C.c_uint64, C.c_double, C.POINTER(ServedResult)]
+    lib.tucker_server_get_stats.argtypes = [v, C.POINTER(ServerStats)]
+    lib.tucker_server_destroy.argtypes = [v]
+    for name in ("tucker_server_create", "tucker_server_submit", "tucker_server_wait", "tucker_server_get_stats",
+                 "tucker_server_destroy"):
+        getattr(lib, name).restype = C.c_int
     for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
                  "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
                  "tucker_quantize", "tucker_ttm_lowp", "tucker_gram_lowp",

@@ -45,6 +45,7 @@ struct tucker_ctx {
     tucker_stats stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pool;   // stage timer events (created on first use)
+    bool async_alloc = false;       // workspace from the stream-ordered allocator (server slots)
 };
 
 namespace {
@@ -967,12 +968,16 @@ void ensure_ws(tucker_ctx* ctx, size_t bytes) {
         throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "workspace exceeds hbm_budget_bytes"};
     if (bytes <= ctx->ws_bytes) return;
     if (ctx->ws) {
-        TK_HIP(hipStreamSynchronize(ctx->stream));
-        (void)hipFree(ctx->ws);
+        if (ctx->async_alloc) {
+            TK_HIP(hipFreeAsync(ctx->ws, ctx->stream));
+        } else {
+            TK_HIP(hipStreamSynchronize(ctx->stream));
+            (void)hipFree(ctx->ws);
+        }
         ctx->ws = nullptr;
         ctx->ws_bytes = 0;
     }
-    hipError_t e = hipMalloc(&ctx->ws, bytes);
+    hipError_t e = ctx->async_alloc ? hipMallocAsync(&ctx->ws, bytes, ctx->stream) : hipMalloc(&ctx->ws, bytes);
     if (e != hipSuccess) {
         ctx->ws = nullptr;
         (void)hipGetLastError();
@@ -1156,8 +1161,9 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
 tucker_status tucker_destroy(tucker_ctx* ctx) {
     if (!ctx) return TUCKER_OK;
     (void)hipSetDevice(ctx->device);
+    if (ctx->ws && ctx->async_alloc) (void)hipFreeAsync(ctx->ws, ctx->stream);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->ws && !ctx->async_alloc) (void)hipFree(ctx->ws);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
@@ -1552,6 +1558,7 @@ const char* tucker_status_string(tucker_status s) {
         case TUCKER_ERR_DEVICE: return "device error";
         case TUCKER_ERR_NUMERICAL: return "numerical error";
         case TUCKER_ERR_UNSUPPORTED: return "unsupported";
+        case TUCKER_ERR_TIMEOUT: return "timed out";
     }
     return "unknown status";
 }
@@ -1565,3 +1572,25 @@ tucker_status tucker_get_stats(const tucker_ctx* ctx, tucker_stats* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- hooks for the request server
+// (C++ linkage; not part of the public C ABI)
+void tk_ctx_set_async_alloc(tucker_ctx* ctx, bool on) { ctx->async_alloc = on; }
+
+void tk_ctx_release_workspace(tucker_ctx* ctx) {
+    if (!ctx->ws) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->async_alloc) {
+        (void)hipFreeAsync(ctx->ws, ctx->stream);
+    } else {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->ws);
+    }
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+}
+
+void tk_ctx_set_run_options(tucker_ctx* ctx, tucker_precision precision, int refine_sweeps) {
+    ctx->opt.precision = precision;
+    ctx->opt.refine_sweeps = refine_sweeps;
+}

@@ -83,3 +83,24 @@ def test_create_without_gpu_reports_device_error():
     h = C.c_void_p()
     assert lib.tucker_create(None, C.byref(h)) == _lib.ERR_DEVICE
     assert not h.value
+
+
+def test_server_without_gpu_and_null_arguments():
+    import torch
+    lib = _lib.lib()
+    o = _lib.ServerOptions()
+    lib.tucker_default_server_options(C.byref(o))
+    assert o.slots == 4 and o.hbm_budget_bytes == 0 and o.init_iters == 20
+    assert lib.tucker_server_create(None, None) == _lib.ERR_INVALID_ARG
+    bad = _lib.ServerOptions()
+    lib.tucker_default_server_options(C.byref(bad))
+    bad.slots = 0
+    h = C.c_void_p()
+    assert lib.tucker_server_create(C.byref(bad), C.byref(h)) == _lib.ERR_INVALID_ARG
+    assert lib.tucker_server_submit(None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.tucker_server_wait(None, 1, 0.0, None) == _lib.ERR_INVALID_ARG
+    assert lib.tucker_server_destroy(None) == _lib.OK
+    if not torch.cuda.is_available():
+        assert lib.tucker_server_create(C.byref(o), C.byref(h)) == _lib.ERR_DEVICE
+        assert not h.value
+    assert lib.tucker_status_string(_lib.ERR_TIMEOUT).decode() == "timed out"
