@@ -271,9 +271,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sweeps", type=int, default=20)
+    ap.add_argument("--sweeps", type=int, default=None, help="sweeps per decomposition (default: the workload's)")
     ap.add_argument("--cpu-sample-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="stack1080", choices=["stack1080", "stack2160"],
+                    help="stack1080: 1080p Y'CbCr, 20 sweeps (the default measurement); stack2160: 4K IPT, 15 sweeps")
     ap.add_argument("--init-iters", type=int, default=20,
                     help="cold-start orthogonal-iteration steps of the T-HOSVD start")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
@@ -301,9 +303,9 @@ def main():
     import paper_2104_04726_amd as tk
     from synth import make_stereo_stack, STACK_CONFIGS
 
-    cfg = STACK_CONFIGS["stack1080"]
+    cfg = STACK_CONFIGS[args.workload]
     H, W, E, ranks = cfg["H"], cfg["W"], cfg["E"], tuple(cfg["ranks"])
-    sweeps = args.sweeps
+    sweeps = args.sweeps if args.sweeps is not None else cfg["sweeps"]
     log(f"generating {H}x{W}x3x{2 * E} stack (seed {cfg['seed']})")
     x32 = make_stereo_stack(H, W, E, cfg["colorspace"], cfg["seed"])
     dims = x32.shape
@@ -345,7 +347,7 @@ def main():
     dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
     kind, amount = work[dominant]
     roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
-    traffic = measured_traffic(dominant) if args.precision == "fp32" else None
+    traffic = measured_traffic(dominant) if (args.precision == "fp32" and args.workload == "stack1080") else None
     roof.update({"kernel": dominant, "traffic": traffic["total_bytes"] if traffic else None,
                  "traffic_unit": "bytes per launch", "traffic_detail": traffic,
                  "per_launch": f"{amount / 1e9:.3f} {'GB' if kind == 'hbm' else 'GFLOP'}"})
@@ -363,7 +365,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8": "fp8_e4m3"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"stack1080: {H}x{W}x3x{2 * E} FP32 Y'CbCr multi-exposure stereo stack, ranks "
+        "config": {"workload": f"{args.workload}: {H}x{W}x3x{2 * E} FP32 {cfg['colorspace']} multi-exposure stereo stack, ranks "
                                f"{list(ranks)}, T-HOSVD start + {sweeps} HOOI sweeps per step"
                                + ("" if args.precision == "fp32" else
                                   f" ({args.precision} contractions, then 1 FP32 refinement sweep)"),

@@ -1228,8 +1228,20 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         } else {
             thosvd(r);
         }
+        // per-sweep fit: ||X||^2 - ||G||^2 (cheap; with the FP32 core its error is amplified by the
+        // cancellation, about 3e-5 at 1080p), or, when a tolerance decides the stop, the explicit
+        // residual ||X - Xhat|| (one more expanding pass per sweep)
+        const bool exact_fits = tol > 0.0;
+        auto sweep_fit = [&](double* slot) {
+            if (exact_fits) {
+                expand_chain(r, p.G, p.U32, nullptr, tensor);
+                TK_HIP(fit_from_resid(p.scal + 0, p.scal + 2, slot, s));
+            } else {
+                core_norm_and_fit(r, slot);
+            }
+        };
         core_from_x(r);
-        core_norm_and_fit(r, p.fits + 0);
+        sweep_fit(p.fits + 0);
         TK_HIP(hipEventRecord(ctx->ev[1], s));
         int done = 0;
         std::vector<double> hf(2);
@@ -1241,7 +1253,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
                 sweep_tree(r);
             else
                 sweep_generic(r);
-            core_norm_and_fit(r, p.fits + k);
+            sweep_fit(p.fits + k);
             done = k;
             if (tol > 0.0) {
                 TK_HIP(hipMemcpyAsync(hf.data(), p.fits + k - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));

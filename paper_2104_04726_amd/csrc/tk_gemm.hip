@@ -118,6 +118,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
     T ra[EA], rb[EB];
 
+    // MK operands: the column offset of k = kbeg + (thread's k column) advances by BK per k-tile;
+    // one division at the start, increments afterwards (loads always advance tile by tile)
+    struct KCol {
+        int64_t kq, kr;
+    };
+    auto kcol_next = [&](const Desc& d, KCol& c) {
+        c.kr += BK;
+        while (c.kr >= d.seg) {
+            c.kr -= d.seg;
+            ++c.kq;
+        }
+    };
+    KCol kca{0, 0}, kcb{0, 0};
+    if (OA == MK) kca = KCol{(kbeg + a_c) / g.a.seg, (kbeg + a_c) % g.a.seg};
+    if (OB == MK) kcb = KCol{(kbeg + b_c) / g.b.seg, (kbeg + b_c) % g.b.seg};
+
     auto load_tiles = [&](int64_t k0) {
         if (OA == KM) {
 #pragma unroll
@@ -128,12 +144,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         } else {
             const int64_t k = k0 + a_c;
             const bool kok = k < kend;
-            const int64_t ko = kok ? coloff(g.a, k) : 0;
+            const int64_t ko = kca.kq * g.a.segstride + kca.kr;
 #pragma unroll
             for (int u = 0; u < EA; ++u) {
                 const int64_t m = m0 + a_r0 + a_step * u;
                 ra[u] = (kok && m < g.M) ? (T)pa[m * g.a.ld + ko] : (T)0;
             }
+            kcol_next(g.a, kca);
         }
         if (OB == KM) {
 #pragma unroll
@@ -144,12 +161,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         } else {
             const int64_t k = k0 + b_c;
             const bool kok = k < kend;
-            const int64_t ko = kok ? coloff(g.b, k) : 0;
+            const int64_t ko = kcb.kq * g.b.segstride + kcb.kr;
 #pragma unroll
             for (int u = 0; u < EB; ++u) {
                 const int64_t n = n0 + b_r0 + b_step * u;
                 rb[u] = (kok && n < g.N) ? (T)pb[n * g.b.ld + ko] : (T)0;
             }
+            kcol_next(g.b, kcb);
         }
     };
     auto store_tiles = [&]() {
