@@ -196,7 +196,7 @@ int64_t lp_gram_partials(int64_t s, int64_t K) {
 }
 
 int gram_splits(int64_t s, int64_t K) {
-    const int64_t t = (s + 63) / 64;       // 64 x 64 FP64 MFMA tiles
+    const int64_t t = (s + 63) / 64;       // lower-triangle 64 x 64 FP64 MFMA tiles
     const int64_t tiles = t * (t + 1) / 2;
     int64_t sp = (kGramTargetBlocks + tiles - 1) / tiles;
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));

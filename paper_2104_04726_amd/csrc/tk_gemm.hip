@@ -16,6 +16,14 @@
 // its L2.
 #include "tk_common.h"
 
+// k-tile depths of the FP32 (128 x 128 tiles) and FP64 (64 x 64 tiles) kernels
+#ifndef TK_F32_BK
+#define TK_F32_BK 32
+#endif
+#ifndef TK_F64_BK
+#define TK_F64_BK 8
+#endif
+
 namespace tk {
 namespace {
 
@@ -327,10 +335,10 @@ hipError_t gemm_f32(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, boo
     GemmArgs g = normalised(gin);
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (epi == EPI_STORE)
-        return acc64 ? by_orient<float, float, float, EPI_STORE, true, 128, 128, 32>(g, oa, ob, s)
-                     : by_orient<float, float, float, EPI_STORE, false, 128, 128, 32>(g, oa, ob, s);
-    if (epi == EPI_ADD) return by_orient<float, float, float, EPI_ADD, false, 128, 128, 32>(g, oa, ob, s);
-    return by_orient<float, float, float, EPI_RESID, false, 128, 128, 32>(g, oa, ob, s);
+        return acc64 ? by_orient<float, float, float, EPI_STORE, true, 128, 128, TK_F32_BK>(g, oa, ob, s)
+                     : by_orient<float, float, float, EPI_STORE, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
+    if (epi == EPI_ADD) return by_orient<float, float, float, EPI_ADD, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
+    return by_orient<float, float, float, EPI_RESID, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
 }
 
 hipError_t gemm_f64(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, bool a_is_f32,
@@ -338,7 +346,7 @@ hipError_t gemm_f64(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, boo
     GemmArgs g = normalised(gin);
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (epi != EPI_STORE) return hipErrorInvalidValue;
-    if (a_is_f32 && b_is_f32) return by_orient<double, float, float, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+    if (a_is_f32 && b_is_f32) return by_orient<double, float, float, EPI_STORE, false, 64, 64, TK_F64_BK>(g, oa, ob, s);
     if (a_is_f32) return by_orient<double, float, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
     if (b_is_f32) return by_orient<double, double, float, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
     return by_orient<double, double, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);

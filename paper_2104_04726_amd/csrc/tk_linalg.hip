@@ -174,6 +174,16 @@ static_assert(TB == 64, "blocked tile kernels assume 64 x 64 tiles");
 
 __device__ __forceinline__ double safe_pivot(double d) { return (d > 1e-13) ? d : 1e-13; }
 
+// 1/d for d > 0: the hardware reciprocal estimate refined by two Newton steps y <- y (2 - d y)
+// (each step squares the relative error; the result is within a few ulp).  Keeps the long-latency
+// IEEE division off the sequential pivot chains below.
+__device__ __forceinline__ double rcp_nr(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(fma(-d, y, 1.0), y, y);
+    y = fma(fma(-d, y, 1.0), y, y);
+    return y;
+}
+
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
     const unsigned long long b = __double_as_longlong(x);
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane);
@@ -195,12 +205,12 @@ __device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
     for (int k = 0; k < SB; ++k) {
         const double d = readlane_f64(a[k], k);          // current pivot
         dk[k] = d;
-        const double inv = 1.0 / safe_pivot(d);
         const double c = a[k];                           // unscaled column entry of this row
+        const double ci = c * rcp_nr(safe_pivot(d));
 #pragma unroll
         for (int j = k + 1; j < SB; ++j) {
             const double cj = readlane_f64(c, j);
-            if (r >= j) a[j] -= c * cj * inv;
+            if (r >= j) a[j] -= ci * cj;
         }
     }
     if (r == 0) {
@@ -208,12 +218,15 @@ __device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
         for (int k = 0; k < SB; ++k)
             if (!(dk[k] > 1e-13)) atomicAdd(shifts, 1);
     }
-    double sq[SB];
+    double sq[SB], rsq[SB];
 #pragma unroll
-    for (int k = 0; k < SB; ++k) sq[k] = sqrt(safe_pivot(dk[k]));
+    for (int k = 0; k < SB; ++k) {
+        sq[k] = sqrt(safe_pivot(dk[k]));
+        rsq[k] = rcp_nr(sq[k]);
+    }
     // L_rj = a_rj / sqrt(d_j) (j < r), L_rr = sqrt(d_r)
 #pragma unroll
-    for (int j = 0; j < SB; ++j) a[j] = (j < r) ? a[j] / sq[j] : ((j == r) ? sq[j] : 0.0);
+    for (int j = 0; j < SB; ++j) a[j] = (j < r) ? a[j] * rsq[j] : ((j == r) ? sq[j] : 0.0);
     if (act) {
 #pragma unroll
         for (int j = 0; j < SB; ++j) A[(o + r) * TS + o + j] = a[j];
@@ -225,7 +238,7 @@ __device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
         double acc = (i == r) ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) acc -= readlane_f64(a[k], i) * x[k];
-        x[i] = (i < r) ? 0.0 : acc / sq[i];
+        x[i] = (i < r) ? 0.0 : acc * rsq[i];
     }
     if (act) {
 #pragma unroll
@@ -286,13 +299,16 @@ __device__ void tile_potrf(double* A, int* shifts) {
 // X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
 __device__ void wave_trtri16(const double* L, int o, double* X) {
     const int c = threadIdx.x & 63;
+    double rd[SB];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) rd[i] = rcp_nr(L[(o + i) * TS + o + i]);
     double x[SB];
 #pragma unroll
     for (int i = 0; i < SB; ++i) {
         double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) acc -= L[(o + i) * TS + o + k] * x[k];
-        x[i] = (i < c) ? 0.0 : acc / L[(o + i) * TS + o + i];
+        x[i] = (i < c) ? 0.0 : acc * rd[i];
     }
     if (c < SB) {
 #pragma unroll
