@@ -57,7 +57,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
 }
 
 template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool ACC64, int BM, int BN,
-          int BK>
+          int BK, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int PADKM = (sizeof(T) == 4) ? 16 : 8;   // row stride of [k][x] tiles
     constexpr int PADMK = (sizeof(T) == 4) ? 4 : 2;    // row stride of [x][k] tiles
@@ -71,8 +71,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int TN = BN / 32;
     typedef typename Mfma<T>::V V;
 
-    __shared__ T As[ASZ];
-    __shared__ T Bs[BSZ];
+    __shared__ __attribute__((aligned(16))) T As[ASZ];
+    __shared__ __attribute__((aligned(16))) T Bs[BSZ];
+    // VEC: both operands k-major (KM) FP32 with 4-aligned contiguous column runs; each thread moves
+    // 4 consecutive columns per row as one 16-byte load and one 16-byte LDS store
+    static_assert(!VEC || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+                           (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0),
+                  "vector loads need FP32 k-major operands and whole float4 per thread");
     if (g.run_if && *g.run_if == 0) return;
 
     const int tid = threadIdx.x;
@@ -115,13 +120,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // KM: the column (m or n) is fixed for the whole K loop
     int64_t a_fix = 0, b_fix = 0;
     bool a_colok = true, b_colok = true;
-    if (OA == KM) {
+    if (OA == KM && !VEC) {
         a_colok = (m0 + a_c) < g.M;
         a_fix = a_colok ? coloff(g.a, m0 + a_c) : 0;
     }
-    if (OB == KM) {
+    if (OB == KM && !VEC) {
         b_colok = (n0 + b_c) < g.N;
         b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
+    }
+    // VEC mapping: thread -> column group c4 (4 columns), rows r0 + step * u
+    constexpr int A4 = BM / 4, B4 = BN / 4;
+    constexpr int av_step = 256 / A4, bv_step = 256 / B4;
+    const int av_c4 = tid % A4, av_r0 = tid / A4;
+    const int bv_c4 = tid % B4, bv_r0 = tid / B4;
+    int64_t av_fix = 0, bv_fix = 0;
+    int av_n = 0, bv_n = 0;      // valid columns of the thread's group (0..4)
+    if (VEC) {
+        const int64_t ca = m0 + 4 * av_c4, cb = n0 + 4 * bv_c4;
+        av_n = (int)((g.M - ca) < 4 ? ((g.M - ca) > 0 ? (g.M - ca) : 0) : 4);
+        bv_n = (int)((g.N - cb) < 4 ? ((g.N - cb) > 0 ? (g.N - cb) : 0) : 4);
+        av_fix = av_n > 0 ? coloff(g.a, ca) : 0;
+        bv_fix = bv_n > 0 ? coloff(g.b, cb) : 0;
     }
 
     T ra[EA], rb[EB];
@@ -142,7 +161,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (OA == MK) kca = KCol{(kbeg + a_c) / g.a.seg, (kbeg + a_c) % g.a.seg};
     if (OB == MK) kcb = KCol{(kbeg + b_c) / g.b.seg, (kbeg + b_c) % g.b.seg};
 
+    auto load_vec = [&](const TA* p, const Desc& d, int64_t fix, int nvalid, int r0, int step, int64_t k0, T* dst,
+                        int count) {
+        for (int u = 0; u < count; ++u) {
+            const int64_t k = k0 + r0 + step * u;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < kend && nvalid > 0) {
+                const TA* src = p + k * d.ld + fix;
+                if (nvalid == 4) {
+                    v = *(const float4*)src;
+                } else {
+                    v.x = src[0];
+                    if (nvalid > 1) v.y = src[1];
+                    if (nvalid > 2) v.z = src[2];
+                }
+            }
+            dst[4 * u + 0] = v.x;
+            dst[4 * u + 1] = v.y;
+            dst[4 * u + 2] = v.z;
+            dst[4 * u + 3] = v.w;
+        }
+    };
     auto load_tiles = [&](int64_t k0) {
+        if constexpr (VEC) {
+            load_vec((const TA*)pa, g.a, av_fix, av_n, av_r0, av_step, k0, ra, EA / 4);
+            load_vec((const TA*)pb, g.b, bv_fix, bv_n, bv_r0, bv_step, k0, rb, EB / 4);
+            return;
+        }
         if (OA == KM) {
 #pragma unroll
             for (int u = 0; u < EA; ++u) {
@@ -179,6 +224,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     };
     auto store_tiles = [&]() {
+        if constexpr (VEC) {
+#pragma unroll
+            for (int u = 0; u < EA / 4; ++u)
+                *(float4*)&As[(av_r0 + av_step * u) * LDA + 4 * av_c4] =
+                    make_float4(ra[4 * u], ra[4 * u + 1], ra[4 * u + 2], ra[4 * u + 3]);
+#pragma unroll
+            for (int u = 0; u < EB / 4; ++u)
+                *(float4*)&Bs[(bv_r0 + bv_step * u) * LDB + 4 * bv_c4] =
+                    make_float4(rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]);
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < EA; ++u) As[(a_r0 + a_step * u) * LDA + a_c] = ra[u];
 #pragma unroll
@@ -298,13 +354,27 @@ dim3 grid_of(const GemmArgs& g) {
     return dim3((unsigned)tiles, 1, (unsigned)(splits > 0 ? splits : 1));
 }
 
+// k-major FP32 operand whose rows are read as aligned runs of 4 contiguous columns
+bool km_vec_ok(const Desc& d) {
+    const bool segok = d.seg >= (int64_t(1) << 61) || (d.seg % 4 == 0 && d.segstride % 4 == 0);
+    return segok && d.ld % 4 == 0 && (((uintptr_t)d.ptr) & 15) == 0;
+}
+
 template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool ACC64, int BM, int BN,
           int BK>
 hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
     dim3 grid = grid_of<T, BM, BN>(g);
     if (grid.x == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK>), grid, dim3(256), 0, s,
-                       g);
+    constexpr bool can_vec = OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+                             (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0;
+    if constexpr (can_vec) {
+        if (km_vec_ok(g.a) && km_vec_ok(g.b)) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, true>), grid, dim3(256), 0, s,
+                               g);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, false>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
