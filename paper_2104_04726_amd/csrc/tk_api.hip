@@ -267,7 +267,7 @@ void build_plan(Plan& p, Arena& a) {
     p.Z = a.take<double>(sR);
     p.Q1 = a.take<double>(sR);
     p.W = a.take<double>(Rm * Rm);
-    p.Wpart_elems = 16 * Rm * Rm;
+    p.Wpart_elems = std::max<int64_t>(16 * Rm * Rm, 8 * sR);
     p.Wpart = a.take<double>(p.Wpart_elems);
     p.Tm = a.take<double>(Rm * Rm);
     p.chol_ws = a.take<char>(chol_counter_ints(Rm) * 4 + 64 + Rm * 8);
@@ -522,6 +522,14 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
 void orth_iter(Run& r, int n, int q, bool cold) {
     Plan& p = r.p;
     const int64_t s = p.s[n], R = p.R[n];
+    // Z = S U has few output tiles ((s/64) x (R/64)); K is split so that the grid fills the chip,
+    // the FP64 partials summed in a fixed order
+    const int64_t tiles = ((s + 63) / 64) * ((R + 63) / 64);
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, s / 128));
+    splits = std::min<int64_t>(splits, p.Wpart_elems / std::max<int64_t>(1, s * R));
+    int64_t ks = (s + splits - 1) / splits;
+    ks = (ks + 15) / 16 * 16;
+    const int nsplit = (int)((s + ks - 1) / ks);
     for (int it = 0; it < q; ++it) {
         GemmArgs g{};
         g.alpha = 1.0;
@@ -530,8 +538,16 @@ void orth_iter(Run& r, int n, int q, bool cold) {
         g.K = s;
         g.a = plain(p.S64, s);      // A(m, k) = S[k][m] (symmetric)
         g.b = plain(p.U64[n], R);
-        g.c = plain(p.Z, R);
-        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+        if (nsplit > 1) {
+            g.k_split = ks;
+            g.c = plain(p.Wpart, R);
+            g.c_zstride = s * R;
+            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+            TK_HIP(tk_sum_splits_f64(p.Wpart, nsplit, s * R, s * R, p.Z, r.st));
+        } else {
+            g.c = plain(p.Z, R);
+            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+        }
         orthonormalize(r, p.Z, false, s, R, p.U64[n], p.U32[n], cold && it < 2);
     }
 }
@@ -1004,7 +1020,16 @@ __global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int6
                                   double* __restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int z = 0; z < nsplit; ++z) s += P[z * zstride + e];
+        int z = 0;
+        for (; z + 4 <= nsplit; z += 4) {     // four loads in flight, summed in split order
+            const double a0 = P[(int64_t)z * zstride + e], a1 = P[(int64_t)(z + 1) * zstride + e];
+            const double a2 = P[(int64_t)(z + 2) * zstride + e], a3 = P[(int64_t)(z + 3) * zstride + e];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; z < nsplit; ++z) s += P[(int64_t)z * zstride + e];
         out[e] = s;
     }
 }
