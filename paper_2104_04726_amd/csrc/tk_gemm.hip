@@ -75,9 +75,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) T Bs[BSZ];
     // VEC: both operands k-major (KM) FP32 with 4-aligned contiguous column runs; each thread moves
     // 4 consecutive columns per row as one 16-byte load and one 16-byte LDS store
+    // VECK: both operands k-contiguous (MK) FP32 data with 4-aligned k runs; each operand tile is 128
+    // float4 vectors, loaded by one half of the workgroup (threads 0..127 A, 128..255 B)
+    constexpr bool VECK = VEC && OA == MK;
     static_assert(!VEC || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
-                           (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0),
-                  "vector loads need FP32 k-major operands and whole float4 per thread");
+                           (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
+                      (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM * BK == 512 &&
+                       BN * BK == 512),
+                  "vector loads need whole float4 per thread");
     if (g.run_if && *g.run_if == 0) return;
 
     const int tid = threadIdx.x;
@@ -128,6 +133,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         b_colok = (n0 + b_c) < g.N;
         b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
     }
+    // VECK mapping: half h = tid / 128 (0: A, 1: B), row = (tid % 128) / (BK / 4), k4 = tid % (BK / 4)
+    const int vk_half = tid >> 7;
+    const int vk_row = (tid & 127) / (BK / 4);
+    const int vk_k4 = tid % (BK / 4);
+    struct KCol4 {
+        int64_t kq, kr;
+    };
+    KCol4 vkc{0, 0};
+    if constexpr (VECK) {
+        const Desc& d = vk_half ? g.b : g.a;
+        const int64_t k = kbeg + 4 * vk_k4;
+        vkc = KCol4{k / d.seg, k % d.seg};
+    }
+    float4 vk_reg = make_float4(0.f, 0.f, 0.f, 0.f);
     // VEC mapping: thread -> column group c4 (4 columns), rows r0 + step * u
     constexpr int A4 = BM / 4, B4 = BN / 4;
     constexpr int av_step = 256 / A4, bv_step = 256 / B4;
@@ -183,6 +202,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     };
     auto load_tiles = [&](int64_t k0) {
+        if constexpr (VECK) {
+            const Desc& d = vk_half ? g.b : g.a;
+            const int64_t rows = vk_half ? g.N : g.M;
+            const int64_t row = (vk_half ? n0 : m0) + vk_row;
+            const int64_t k = k0 + 4 * vk_k4;
+            const TA* p = (const TA*)d.ptr;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < rows) {
+                const TA* src = p + row * d.ld + vkc.kq * d.segstride + vkc.kr;
+                if (k + 4 <= kend) {
+                    v = *(const float4*)src;
+                } else {
+                    if (k < kend) v.x = src[0];
+                    if (k + 1 < kend) v.y = src[1];
+                    if (k + 2 < kend) v.z = src[2];
+                }
+            }
+            vk_reg = v;
+            vkc.kr += BK;
+            while (vkc.kr >= d.seg) {
+                vkc.kr -= d.seg;
+                ++vkc.kq;
+            }
+            return;
+        }
         if constexpr (VEC) {
             load_vec((const TA*)pa, g.a, av_fix, av_n, av_r0, av_step, k0, ra, EA / 4);
             load_vec((const TA*)pb, g.b, bv_fix, bv_n, bv_r0, bv_step, k0, rb, EB / 4);
@@ -224,6 +268,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     };
     auto store_tiles = [&]() {
+        if constexpr (VECK) {
+            T* dst = (vk_half ? Bs : As) + vk_row * (vk_half ? LDB : LDA) + 4 * vk_k4;
+            dst[0] = (T)vk_reg.x;
+            dst[1] = (T)vk_reg.y;
+            dst[2] = (T)vk_reg.z;
+            dst[3] = (T)vk_reg.w;
+            return;
+        }
         if constexpr (VEC) {
 #pragma unroll
             for (int u = 0; u < EA / 4; ++u)
@@ -365,10 +417,12 @@ template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool AC
 hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
     dim3 grid = grid_of<T, BM, BN>(g);
     if (grid.x == 0) return hipSuccess;
-    constexpr bool can_vec = OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
-                             (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0;
+    constexpr bool can_vec = (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+                              (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
+                             (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM * BK == 512 &&
+                              BN * BK == 512);
     if constexpr (can_vec) {
-        if (km_vec_ok(g.a) && km_vec_ok(g.b)) {
+        if (km_vec_ok(g.a) && km_vec_ok(g.b) && (OA == KM || g.k_split % 4 == 0)) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, true>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();

@@ -80,6 +80,9 @@ def test_ttm_matches_definition(ctx, shape, mode, r):
     ((2, 257, 3, 14), 1),             # ragged s, folded k of 42
     ((40, 20, 30), 1),                # small-mode Gram
     ((64, 48, 3, 6), 0),              # small, s = 64
+    ((5, 300, 24), 1),                # k runs of 24: 16-byte vector loads
+    ((200, 96), 0),                   # contiguous rows, vector loads, ragged tiles
+    ((130, 7, 4), 0),                 # k = 28 not a multiple of the tile depth (vector tail)
 ])
 def test_gram_matches_definition(ctx, shape, mode):
     rng = np.random.default_rng(1 + mode)
