@@ -21,7 +21,7 @@
 #define TK_F32_BK 32
 #endif
 #ifndef TK_F64_BK
-#define TK_F64_BK 8
+#define TK_F64_BK 16
 #endif
 
 namespace tk {
@@ -80,9 +80,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr bool VECK = VEC && OA == MK;
     static_assert(!VEC || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
                            (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
-                      (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM * BK == 512 &&
-                       BN * BK == 512),
+                      (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
+                       (BM * BK == 512 || BM * BK == 1024)),
                   "vector loads need whole float4 per thread");
+    constexpr bool VK2 = VECK && BM * BK == 1024;   // every thread loads one vector of A and one of B
     if (g.run_if && *g.run_if == 0) return;
 
     const int tid = threadIdx.x;
@@ -133,9 +134,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         b_colok = (n0 + b_c) < g.N;
         b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
     }
-    // VECK mapping: half h = tid / 128 (0: A, 1: B), row = (tid % 128) / (BK / 4), k4 = tid % (BK / 4)
-    const int vk_half = tid >> 7;
-    const int vk_row = (tid & 127) / (BK / 4);
+    // VECK mapping: 512-element tiles: half h = tid / 128 (0: A, 1: B), row = (tid % 128) / (BK / 4);
+    // 1024-element tiles (VK2): every thread one vector of each operand, row = tid / (BK / 4)
+    const int vk_half = VK2 ? 0 : (tid >> 7);
+    const int vk_row = VK2 ? tid / (BK / 4) : (tid & 127) / (BK / 4);
     const int vk_k4 = tid % (BK / 4);
     struct KCol4 {
         int64_t kq, kr;
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         const int64_t k = kbeg + 4 * vk_k4;
         vkc = KCol4{k / d.seg, k % d.seg};
     }
-    float4 vk_reg = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 vk_reg = make_float4(0.f, 0.f, 0.f, 0.f), vk_reg2 = make_float4(0.f, 0.f, 0.f, 0.f);
     // VEC mapping: thread -> column group c4 (4 columns), rows r0 + step * u
     constexpr int A4 = BM / 4, B4 = BN / 4;
     constexpr int av_step = 256 / A4, bv_step = 256 / B4;
@@ -203,23 +205,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     };
     auto load_tiles = [&](int64_t k0) {
         if constexpr (VECK) {
-            const Desc& d = vk_half ? g.b : g.a;
-            const int64_t rows = vk_half ? g.N : g.M;
-            const int64_t row = (vk_half ? n0 : m0) + vk_row;
-            const int64_t k = k0 + 4 * vk_k4;
-            const TA* p = (const TA*)d.ptr;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < rows) {
-                const TA* src = p + row * d.ld + vkc.kq * d.segstride + vkc.kr;
-                if (k + 4 <= kend) {
-                    v = *(const float4*)src;
-                } else {
-                    if (k < kend) v.x = src[0];
-                    if (k + 1 < kend) v.y = src[1];
-                    if (k + 2 < kend) v.z = src[2];
+            auto ld4 = [&](const Desc& d, int64_t rows, int64_t row, int64_t k) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (row < rows) {
+                    const TA* src = (const TA*)d.ptr + row * d.ld + vkc.kq * d.segstride + vkc.kr;
+                    if (k + 4 <= kend) {
+                        v = *(const float4*)src;
+                    } else {
+                        if (k < kend) v.x = src[0];
+                        if (k + 1 < kend) v.y = src[1];
+                        if (k + 2 < kend) v.z = src[2];
+                    }
                 }
+                return v;
+            };
+            const int64_t k = k0 + 4 * vk_k4;
+            // A and B share the k position (same segment structure is required of VK2 operands)
+            if (VK2) {
+                vk_reg = ld4(g.a, g.M, m0 + vk_row, k);
+                vk_reg2 = ld4(g.b, g.N, n0 + vk_row, k);
+            } else {
+                vk_reg = vk_half ? ld4(g.b, g.N, n0 + vk_row, k) : ld4(g.a, g.M, m0 + vk_row, k);
             }
-            vk_reg = v;
+            const Desc& d = vk_half ? g.b : g.a;
             vkc.kr += BK;
             while (vkc.kr >= d.seg) {
                 vkc.kr -= d.seg;
@@ -274,6 +282,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             dst[1] = (T)vk_reg.y;
             dst[2] = (T)vk_reg.z;
             dst[3] = (T)vk_reg.w;
+            if (VK2) {
+                T* d2 = Bs + vk_row * LDB + 4 * vk_k4;
+                d2[0] = (T)vk_reg2.x;
+                d2[1] = (T)vk_reg2.y;
+                d2[2] = (T)vk_reg2.z;
+                d2[3] = (T)vk_reg2.w;
+            }
             return;
         }
         if constexpr (VEC) {
@@ -419,10 +434,13 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
     if (grid.x == 0) return hipSuccess;
     constexpr bool can_vec = (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
                               (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
-                             (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM * BK == 512 &&
-                              BN * BK == 512);
+                             (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
+                              (BM * BK == 512 || BM * BK == 1024));
     if constexpr (can_vec) {
-        if (km_vec_ok(g.a) && km_vec_ok(g.b) && (OA == KM || g.k_split % 4 == 0)) {
+        // the 1024-element form advances one k position for both operands: same segment layout
+        const bool same_seg = !(OA == MK && BM * BK == 1024) ||
+                              (g.a.seg == g.b.seg && g.a.segstride == g.b.segstride);
+        if (km_vec_ok(g.a) && km_vec_ok(g.b) && same_seg && (OA == KM || g.k_split % 4 == 0)) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, true>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
