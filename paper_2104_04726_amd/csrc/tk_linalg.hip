@@ -125,38 +125,50 @@ __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t
     }
 }
 
-// C = beta*C + alpha * A * op(B), op(B) = B^T when transB.  256 threads; thread t owns the 4x4
-// block at rows 4 (t / 16), columns 4 (t % 16) (TB = 64).
+// C = beta*C + alpha * A * op(B), op(B) = B^T when transB, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  256 threads = 4 waves; wave w owns the 32 x 32 quadrant at rows
+// 32 (w & 1), columns 32 (w >> 1) as 2 x 2 tiles of 16 x 16.  Fragment layouts: A lane l holds
+// (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), the result lane l holds
+// column l % 16 and rows l / 16 + 4 v.  C may alias A or B (results are written after a barrier).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 __device__ void tile_gemm(double* C, const double* A, const double* B, bool transB, double alpha,
                           double beta) {
     static_assert(TB == 64, "tile_gemm assumes 64 x 64 tiles and 256 threads");
-    const int r0 = (threadIdx.x >> 4) * 4;
-    const int c0 = (threadIdx.x & 15) * 4;
-    double acc[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = 32 * (wave & 1), col0 = 32 * (wave >> 1);
+    const int fr = lane & 15, fk = lane >> 4;
+    f64x4_t acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int k = 0; k < TB; ++k) {
-        double av[4], bv[4];
+    for (int k0 = 0; k0 < TB; k0 += 4) {
+        const int k = k0 + fk;
+        double av[2], bv[2];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = A[(r0 + a) * TS + k];
+        for (int i = 0; i < 2; ++i) av[i] = A[(row0 + 16 * i + fr) * TS + k];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = transB ? B[(c0 + b) * TS + k] : B[k * TS + c0 + b];
+        for (int j = 0; j < 2; ++j) {
+            const int c = col0 + 16 * j + fr;
+            bv[j] = transB ? B[c * TS + k] : B[k * TS + c];
+        }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();   // C may alias A or B
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            double* d = &C[(r0 + a) * TS + c0 + b];
-            *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[a][b];
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double* d = &C[(row0 + 16 * i + fk + 4 * v) * TS + col0 + 16 * j + fr];
+                *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[i][j][v];
+            }
     __syncthreads();
 }
 
