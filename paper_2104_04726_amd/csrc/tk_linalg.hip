@@ -24,6 +24,7 @@ namespace {
 #endif
 constexpr int TB = TK_CHOL_TB;
 constexpr int TS = TB + 1;                  // padded LDS row stride
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr long long kMaxSpin = 1ll << 24;   // bounded waits (x ~64 cycles of sleep each)
 
 struct CholArgs {
@@ -130,8 +131,6 @@ __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t
 // 32 (w & 1), columns 32 (w >> 1) as 2 x 2 tiles of 16 x 16.  Fragment layouts: A lane l holds
 // (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), the result lane l holds
 // column l % 16 and rows l / 16 + 4 v.  C may alias A or B (results are written after a barrier).
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
-
 __device__ void tile_gemm(double* C, const double* A, const double* B, bool transB, double alpha,
                           double beta) {
     static_assert(TB == 64, "tile_gemm assumes 64 x 64 tiles and 256 threads");
@@ -259,42 +258,49 @@ __device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
 }
 
 // In-LDS Cholesky of the 64 x 64 tile A (lower; upper zeroed).  Right-looking over the four 16-wide
-// block columns: wave factor + inverse of the diagonal block, TRSM of the block column below,
-// SYRK update of the trailing lower triangle.
+// block columns: wave 0 factors the diagonal block and inverts it (Y = L_bb^-1); the block column
+// below, L_ib = A_ib Y^T, and the trailing update A_ij -= L_ib L_jb^T (i >= j, 16 x 16 tiles) run on
+// the FP64 matrix cores, one 16 x 16 tile per wave.
 __device__ void tile_potrf(double* A, int* shifts) {
     __shared__ double Y[SB * SB];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fk = lane >> 4;
     for (int b = 0; b < TB / SB; ++b) {
         const int o = b * SB;
         if (tid < 64) wave_potrf16(A, o, Y, shifts);
         __syncthreads();
-        const int rows = TB - o - SB;
-        if (rows > 0) {
-            // L_ic = sum_{k <= c} A_ik Y_ck for i >= o + 16, c in the block (Y = L_bb^-1)
-            double vals[3];
-            int cnt = 0;
-            for (int e = tid; e < rows * SB; e += blockDim.x) {
-                const int i = o + SB + e / SB, c = e % SB;
-                double acc = 0.0;
-                for (int k = 0; k <= c; ++k) acc += A[i * TS + o + k] * Y[c * SB + k];
-                vals[cnt++] = acc;
-            }
-            __syncthreads();
-            cnt = 0;
-            for (int e = tid; e < rows * SB; e += blockDim.x) {
-                const int i = o + SB + e / SB, c = e % SB;
-                A[i * TS + o + c] = vals[cnt++];
-            }
-            __syncthreads();
-            // trailing lower triangle: A_ij -= sum_c L_ic L_jc, o+16 <= j <= i
-            for (int e = tid; e < rows * rows; e += blockDim.x) {
-                const int ii = e / rows, jj = e % rows;
-                if (jj > ii) continue;
-                const int i = o + SB + ii, j = o + SB + jj;
-                double acc = 0.0;
+        const int nt = (TB - o - SB) / SB;      // 16-row tiles below the diagonal block
+        if (nt > 0) {
+            if (wave < nt) {
+                // L_ic = sum_k A_ik Y_ck: A fragment (row fr, k), B fragment (k, column fr) = Y[fr][k]
+                const int r0 = o + SB + SB * wave;
+                f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < SB; ++c) acc += A[i * TS + o + c] * A[j * TS + o + c];
-                A[i * TS + j] -= acc;
+                for (int st = 0; st < SB / 4; ++st) {
+                    const int k = 4 * st + fk;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(r0 + fr) * TS + o + k], Y[fr * SB + k], acc, 0, 0,
+                                                               0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A[(r0 + fk + 4 * v) * TS + o + fr] = acc[v];
+            }
+            __syncthreads();
+            // trailing lower triangle by 16 x 16 tile pairs (I >= J)
+            const int npairs = nt * (nt + 1) / 2;
+            for (int pidx = wave; pidx < npairs; pidx += 4) {
+                int I = 0;
+                while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+                const int J = pidx - I * (I + 1) / 2;
+                const int ri = o + SB + SB * I, rj = o + SB + SB * J;
+                f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < SB / 4; ++st) {
+                    const int k = 4 * st + fk;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(ri + fr) * TS + o + k], A[(rj + fr) * TS + o + k],
+                                                               acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A[(ri + fk + 4 * v) * TS + rj + fr] -= acc[v];
             }
             __syncthreads();
         }
