@@ -344,25 +344,36 @@ __device__ void tile_trtri(const double* L, double* X) {
     __syncthreads();
     wave_trtri16(L, (tid >> 6) * SB, X);     // wave w inverts diagonal block w
     __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fk = lane >> 4;
     for (int bi = 1; bi < TB / SB; ++bi) {
-        // T_j = sum_{k=j}^{bi-1} L_{bi,k} X_{k,j}   for j < bi
-        for (int e = tid; e < bi * SB * SB; e += blockDim.x) {
-            const int bj = e / (SB * SB), rr = (e / SB) % SB, cc = e % SB;
-            double acc = 0.0;
+        // wave j < bi: T_j = sum_{k=j}^{bi-1} L_{bi,k} X_{k,j} on the matrix cores
+        if (wave < bi) {
+            const int bj = wave;
+            f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
             for (int bk = bj; bk < bi; ++bk)
 #pragma unroll
-                for (int k = 0; k < SB; ++k)
-                    acc += L[(bi * SB + rr) * TS + bk * SB + k] * X[(bk * SB + k) * TS + bj * SB + cc];
-            Tm[e] = acc;
+                for (int st = 0; st < SB / 4; ++st) {
+                    const int k = bk * SB + 4 * st + fk;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(L[(bi * SB + fr) * TS + k], X[k * TS + bj * SB + fr],
+                                                               acc, 0, 0, 0);
+                }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Tm[bj * SB * SB + (fk + 4 * v) * SB + fr] = acc[v];
         }
         __syncthreads();
-        // X_{bi,j} = -X_{bi,bi} T_j
-        for (int e = tid; e < bi * SB * SB; e += blockDim.x) {
-            const int bj = e / (SB * SB), rr = (e / SB) % SB, cc = e % SB;
-            double acc = 0.0;
+        // wave j < bi: X_{bi,j} = -X_{bi,bi} T_j
+        if (wave < bi) {
+            const int bj = wave;
+            f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int k = 0; k < SB; ++k) acc += X[(bi * SB + rr) * TS + bi * SB + k] * Tm[bj * SB * SB + k * SB + cc];
-            X[(bi * SB + rr) * TS + bj * SB + cc] = -acc;
+            for (int st = 0; st < SB / 4; ++st) {
+                const int k = 4 * st + fk;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[(bi * SB + fr) * TS + bi * SB + k],
+                                                           Tm[bj * SB * SB + k * SB + fr], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[(bi * SB + fk + 4 * v) * TS + bj * SB + fr] = -acc[v];
         }
         __syncthreads();
     }
