@@ -57,7 +57,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
 }
 
 template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool ACC64, int BM, int BN,
-          int BK, bool VEC>
+          int BK, int VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int PADKM = (sizeof(T) == 4) ? 16 : 8;   // row stride of [k][x] tiles
     constexpr int PADMK = (sizeof(T) == 4) ? 4 : 2;    // row stride of [x][k] tiles
@@ -77,8 +77,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // 4 consecutive columns per row as one 16-byte load and one 16-byte LDS store
     // VECK: both operands k-contiguous (MK) FP32 data with 4-aligned k runs; each operand tile is 128
     // float4 vectors, loaded by one half of the workgroup (threads 0..127 A, 128..255 B)
-    constexpr bool VECK = VEC && OA == MK;
-    static_assert(!VEC || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+    constexpr bool VECK = VEC == 4 && OA == MK;
+    // V2K: k-contiguous FP32 operands whose k runs are only 2-aligned (e.g. 42-long pixel fibres):
+    // 8-byte vectors, two of each operand per thread (1024-element tiles)
+    constexpr bool V2K = VEC == 2;
+    static_assert(VEC != 2 || (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
+                               BM * BK == 1024),
+                  "8-byte vector loads need k-contiguous FP32 operands and 1024-element tiles");
+    static_assert(VEC != 4 || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
                            (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
                       (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
                        (BM * BK == 512 || BM * BK == 1024)),
@@ -126,11 +132,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // KM: the column (m or n) is fixed for the whole K loop
     int64_t a_fix = 0, b_fix = 0;
     bool a_colok = true, b_colok = true;
-    if (OA == KM && !VEC) {
+    if (OA == KM && VEC != 4) {
         a_colok = (m0 + a_c) < g.M;
         a_fix = a_colok ? coloff(g.a, m0 + a_c) : 0;
     }
-    if (OB == KM && !VEC) {
+    if (OB == KM && VEC != 4) {
         b_colok = (n0 + b_c) < g.N;
         b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
     }
@@ -149,6 +155,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         vkc = KCol4{k / d.seg, k % d.seg};
     }
     float4 vk_reg = make_float4(0.f, 0.f, 0.f, 0.f), vk_reg2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // V2K mapping: vector index tid + 256 u (u = 0, 1) -> row (tid / (BK/2)) + 32 u, k pair tid % (BK/2)
+    constexpr int v2_rstep = 256 / (BK / 2 > 0 ? BK / 2 : 1);
+    const int v2_row = tid / (BK / 2 > 0 ? BK / 2 : 1);
+    const int v2_kw = tid % (BK / 2 > 0 ? BK / 2 : 1);
+    KCol4 v2c{0, 0};
+    if constexpr (V2K) {
+        const int64_t k = kbeg + 2 * v2_kw;
+        v2c = KCol4{k / g.a.seg, k % g.a.seg};
+    }
+    float2 v2a[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float2 v2b[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    auto ld2 = [&](const Desc& d, int64_t rows, int64_t row, int64_t k) {
+        float2 v = make_float2(0.f, 0.f);
+        if (row < rows) {
+            const TA* src = (const TA*)d.ptr + row * d.ld + v2c.kq * d.segstride + v2c.kr;
+            if (k + 2 <= kend) {
+                v = *(const float2*)src;
+            } else if (k < kend) {
+                v.x = src[0];
+            }
+        }
+        return v;
+    };
     // VEC mapping: thread -> column group c4 (4 columns), rows r0 + step * u
     constexpr int A4 = BM / 4, B4 = BN / 4;
     constexpr int av_step = 256 / A4, bv_step = 256 / B4;
@@ -156,7 +185,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int bv_c4 = tid % B4, bv_r0 = tid / B4;
     int64_t av_fix = 0, bv_fix = 0;
     int av_n = 0, bv_n = 0;      // valid columns of the thread's group (0..4)
-    if (VEC) {
+    if (VEC == 4 && OA == KM) {
         const int64_t ca = m0 + 4 * av_c4, cb = n0 + 4 * bv_c4;
         av_n = (int)((g.M - ca) < 4 ? ((g.M - ca) > 0 ? (g.M - ca) : 0) : 4);
         bv_n = (int)((g.N - cb) < 4 ? ((g.N - cb) > 0 ? (g.N - cb) : 0) : 4);
@@ -235,7 +264,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             }
             return;
         }
-        if constexpr (VEC) {
+        if constexpr (V2K) {
+            const int64_t k = k0 + 2 * v2_kw;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int row = v2_row + v2_rstep * u;
+                v2a[u] = ld2(g.a, g.M, m0 + row, k);
+                v2b[u] = ld2(g.b, g.N, n0 + row, k);
+            }
+            v2c.kr += BK;
+            while (v2c.kr >= g.a.seg) {
+                v2c.kr -= g.a.seg;
+                ++v2c.kq;
+            }
+            return;
+        }
+        if constexpr (VEC == 4 && OA == KM) {
             load_vec((const TA*)pa, g.a, av_fix, av_n, av_r0, av_step, k0, ra, EA / 4);
             load_vec((const TA*)pb, g.b, bv_fix, bv_n, bv_r0, bv_step, k0, rb, EB / 4);
             return;
@@ -291,7 +335,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             }
             return;
         }
-        if constexpr (VEC) {
+        if constexpr (V2K) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int row = v2_row + v2_rstep * u;
+                T* da = As + row * LDA + 2 * v2_kw;
+                da[0] = (T)v2a[u].x;
+                da[1] = (T)v2a[u].y;
+                T* db = Bs + row * LDB + 2 * v2_kw;
+                db[0] = (T)v2b[u].x;
+                db[1] = (T)v2b[u].y;
+            }
+            return;
+        }
+        if constexpr (VEC == 4 && OA == KM) {
 #pragma unroll
             for (int u = 0; u < EA / 4; ++u)
                 *(float4*)&As[(av_r0 + av_step * u) * LDA + 4 * av_c4] =
@@ -441,12 +498,25 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
         const bool same_seg = !(OA == MK && BM * BK == 1024) ||
                               (g.a.seg == g.b.seg && g.a.segstride == g.b.segstride);
         if (km_vec_ok(g.a) && km_vec_ok(g.b) && same_seg && (OA == KM || g.k_split % 4 == 0)) {
-            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, true>), grid, dim3(256), 0, s,
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 4>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, false>), grid, dim3(256), 0, s, g);
+    constexpr bool can_vec2 = OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
+                              BM * BK == 1024;
+    if constexpr (can_vec2) {
+        auto ok2 = [](const Desc& d) {
+            const bool segok = d.seg >= (int64_t(1) << 61) || (d.seg % 2 == 0 && d.segstride % 2 == 0);
+            return segok && d.ld % 2 == 0 && (((uintptr_t)d.ptr) & 7) == 0;
+        };
+        if (ok2(g.a) && ok2(g.b) && g.a.seg == g.b.seg && g.a.segstride == g.b.segstride && g.k_split % 2 == 0) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 2>), grid, dim3(256), 0, s,
+                               g);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 0>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

@@ -83,6 +83,8 @@ def test_ttm_matches_definition(ctx, shape, mode, r):
     ((5, 300, 24), 1),                # k runs of 24: 16-byte vector loads
     ((200, 96), 0),                   # contiguous rows, vector loads, ragged tiles
     ((130, 7, 4), 0),                 # k = 28 not a multiple of the tile depth (vector tail)
+    ((4, 150, 18), 1),                # k runs of 18: 8-byte vector loads
+    ((3, 90, 42), 1),                 # k runs of 42 (pixel fibres): 8-byte vector loads
 ])
 def test_gram_matches_definition(ctx, shape, mode):
     rng = np.random.default_rng(1 + mode)
