@@ -296,6 +296,7 @@ struct Run {
     std::vector<Mark> marks;
     size_t next_ev = 0;
     int inner_override = 0;     // orthogonal-iteration steps per update in refinement sweeps
+    double orth_tol = 1e-12;    // CholeskyQR second-pass threshold on max |Q^T Q - I|
 
     int record() {
         if (next_ev >= ctx->pool.size()) {
@@ -488,7 +489,8 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
 // the host.  Column scaling makes the first pass nearly exact when the columns of Z are close to
 // orthogonal, which is the case once the leading columns have settled.  Each pass maps the basis
 // by an invertible triangular factor, so the column space is that of Z.
-constexpr double kOrthTol = 1e-12;
+constexpr double kOrthTol = 1e-12;     // FP32 sweeps: the factors are orthonormal to FP64 rounding
+constexpr double kOrthTolLowp = 1e-8;  // reduced-precision sweeps: far below their 2^-8..2^-4 operands
 
 void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
                     bool cold) {
@@ -503,7 +505,7 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     if (!cold) {
         // pass 2 only where needed: need = p.shifts[2], counted in p.shifts[1]
         int* need = p.shifts + 2;
-        TK_HIP(orth_check(p.W, cols, kOrthTol, p.red, need, p.shifts + 1, r.st));
+        TK_HIP(orth_check(p.W, cols, r.orth_tol, p.red, need, p.shifts + 1, r.st));
         TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st, need));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64, need);
         TK_HIP(copy_unless(need, p.Q1, U64, rows * cols, r.st));
@@ -1270,7 +1272,10 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         TK_HIP(hipEventRecord(ctx->ev[1], s));
         int done = 0;
         std::vector<double> hf(2);
-        if (p.prec != 0) lp_convert_x(r);
+        if (p.prec != 0) {
+            lp_convert_x(r);
+            r.orth_tol = kOrthTolLowp;
+        }
         for (int k = 1; k <= max_iters; ++k) {
             if (p.prec != 0)
                 sweep_tree_lp(r);
@@ -1290,6 +1295,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         // large-mode update iterates to the leading subspace of its FP32 Gram (kRefineInner steps),
         // since the warm start carries the reduced-precision error
         r.inner_override = kRefineInner;
+        r.orth_tol = kOrthTol;
         for (int k = 1; k <= p.refine; ++k) {
             sweep_tree(r);
             core_norm_and_fit(r, p.fits + done + k);

@@ -131,7 +131,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
 constexpr int LBM = 128, LBN = 128, LBK = 64;
 
 template <int P, int OB, int OUTP, bool VEC>
-__global__ __launch_bounds__(256) void gemm_lp_kernel(LpGemmArgs g) {
+__global__ __launch_bounds__(256, 2) void gemm_lp_kernel(LpGemmArgs g) {
     typedef typename Codec<P>::S S;
     typedef typename Vec8<P>::T V8;
     constexpr int ES = (int)sizeof(S);
