@@ -203,7 +203,7 @@ def serve(args):
                 "wall_s": round(wall, 3)}
 
     # warm-up (kernels loaded, memory pool primed) on one request of every size
-    with tk.Server(0, slots=args.slots) as srv:
+    with tk.Server(0, slots=args.slots, use_graphs=not args.no_serve_graphs) as srv:
         warm = [dict(H=H, W=W, E=7, ranks=(H // 4, W // 4, 3, 13), t_arrive=0.0) for (H, W) in sizes]
         run(srv, warm, open_loop=False)
         log(f"open loop: {len(reqs)} requests, Poisson 40/s, {args.slots} slots")
@@ -280,7 +280,10 @@ def main():
                     help="cold-start orthogonal-iteration steps of the T-HOSVD start")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each sweep as a HIP graph on a side stream (no per-stage timers)")
     ap.add_argument("--serve", action="store_true", help="run the served-execution benchmark instead")
+    ap.add_argument("--no-serve-graphs", action="store_true", help="serving slots launch kernel by kernel")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--saturated", type=int, default=128)
     ap.add_argument("--slots", type=int, default=4)
@@ -312,7 +315,12 @@ def main():
     x = torch.from_numpy(x32).to("cuda:0")
     torch.cuda.synchronize()
 
-    ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters)
+    if args.graphs:
+        side = torch.cuda.Stream()
+        ctx = tk.Context(0, stream=side, timing=False, precision=args.precision, refine_sweeps=1,
+                         init_iters=args.init_iters, use_graphs=True)
+    else:
+        ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
@@ -344,13 +352,15 @@ def main():
         if name in work:
             entry.update(roofline_of(*work[name], per))
         stages[name] = entry
-    dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
-    kind, amount = work[dominant]
-    roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
-    traffic = measured_traffic(dominant) if (args.precision == "fp32" and args.workload == "stack1080") else None
-    roof.update({"kernel": dominant, "traffic": traffic["total_bytes"] if traffic else None,
-                 "traffic_unit": "bytes per launch", "traffic_detail": traffic,
-                 "per_launch": f"{amount / 1e9:.3f} {'GB' if kind == 'hbm' else 'GFLOP'}"})
+    roof = None
+    if any(n in work for n in stages):
+        dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
+        kind, amount = work[dominant]
+        roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
+        traffic = measured_traffic(dominant) if (args.precision == "fp32" and args.workload == "stack1080") else None
+        roof.update({"kernel": dominant, "traffic": traffic["total_bytes"] if traffic else None,
+                     "traffic_unit": "bytes per launch", "traffic_detail": traffic,
+                     "per_launch": f"{amount / 1e9:.3f} {'GB' if kind == 'hbm' else 'GFLOP'}"})
 
     out = {
         "metric": "HOOI sweeps/s",

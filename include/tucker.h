@@ -73,7 +73,9 @@ typedef struct {
     int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1)   */
     int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD     */
     double inner_tol;            /* reserved (0)                                              */
-    int use_graphs;              /* reserved (0)                                              */
+    int use_graphs;              /* 1: capture one sweep as a HIP graph and replay it for every
+                                    sweep (needs a non-NULL stream, timing 0 and tol 0; otherwise
+                                    the sweeps are launched one kernel at a time)              */
     size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
     uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
     int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats)   */
@@ -258,6 +260,7 @@ typedef struct {
     int inner_iters;             /* as in tucker_options                                      */
     int init_iters;
     uint64_t seed;
+    int use_graphs;              /* 1: slots replay each request's sweep as a HIP graph       */
 } tucker_server_options;
 
 typedef struct {
@@ -292,7 +295,8 @@ typedef struct {
     int peak_running;            /* largest number of requests running at once               */
 } tucker_server_stats;
 
-/* Defaults: device 0, 4 slots, budget 0 (90% of free memory), inner_iters 1, init_iters 20. */
+/* Defaults: device 0, 4 slots, budget 0 (90% of free memory), inner_iters 1, init_iters 20,
+ * use_graphs 1. */
 void tucker_default_server_options(tucker_server_options* o);
 /* ERR_DEVICE without a usable GPU; ERR_INVALID_ARG for bad options. */
 tucker_status tucker_server_create(const tucker_server_options* opts, tucker_server** out);

@@ -83,7 +83,7 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, inner_iters: int = 1, init_iters: int = 20,
                  seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
-                 refine_sweeps: int = 1, timing: bool = False):
+                 refine_sweeps: int = 1, timing: bool = False, use_graphs: bool = False):
         import torch
         lib = _lib.lib()
         opts = _lib.Options()
@@ -100,6 +100,7 @@ class Context:
         opts.precision = _PRECISIONS[precision]
         opts.refine_sweeps = int(refine_sweeps)
         opts.timing = 1 if timing else 0
+        opts.use_graphs = 1 if use_graphs else 0
         self.device = int(device)
         self._h = C.c_void_p()
         _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))
@@ -343,11 +344,12 @@ class Server:
     tensor must stay alive until wait() returns its result."""
 
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0, inner_iters: int = 1,
-                 init_iters: int = 20, seed: int = 0x5EED):
+                 init_iters: int = 20, seed: int = 0x5EED, use_graphs: bool = True):
         o = _lib.ServerOptions()
         _lib.lib().tucker_default_server_options(C.byref(o))
         o.device, o.slots, o.hbm_budget_bytes = int(device), int(slots), int(hbm_budget_bytes)
         o.inner_iters, o.init_iters, o.seed = int(inner_iters), int(init_iters), int(seed)
+        o.use_graphs = 1 if use_graphs else 0
         h = C.c_void_p()
         _check(_lib.lib().tucker_server_create(C.byref(o), C.byref(h)))
         self._h = h

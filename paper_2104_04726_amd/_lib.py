@@ -61,6 +61,7 @@ class ServerOptions(C.Structure):
         ("inner_iters", C.c_int),
         ("init_iters", C.c_int),
         ("seed", C.c_uint64),
+        ("use_graphs", C.c_int),
     ]
 
 

@@ -31,6 +31,8 @@
 using namespace tk;
 
 hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s);
+hipError_t tk_set_int(int* p, int v, hipStream_t s);
+hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_t s);
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
                           hipStream_t s);
 
@@ -1016,8 +1018,30 @@ void bind(tucker_ctx* ctx, Plan& p) {
 
 }  // namespace
 
+// captured sweep graph: released after the stream has drained
+struct GraphHold {
+    hipStream_t s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphHold() {
+        if (exec || graph) (void)hipStreamSynchronize(s);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 // helpers defined in this TU but called through extern declarations above
 namespace {
+__global__ void set_int_kernel(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+__global__ void fit_push_kernel(const double* __restrict__ src, int* counter, double* __restrict__ fits) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int k = *counter;
+        fits[k] = *src;
+        *counter = k + 1;
+    }
+}
 __global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int64_t n, int64_t zstride,
                                   double* __restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -1052,6 +1076,15 @@ __global__ void resid_kernel(const float* __restrict__ X, const float* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 }  // namespace
+
+hipError_t tk_set_int(int* p, int v, hipStream_t s) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_t s) {
+    hipLaunchKernelGGL(fit_push_kernel, dim3(1), dim3(64), 0, s, src, counter, fits);
+    return hipGetLastError();
+}
 
 hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s) {
     int64_t g = (n + 255) / 256;
@@ -1276,13 +1309,41 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
             lp_convert_x(r);
             r.orth_tol = kOrthTolLowp;
         }
-        for (int k = 1; k <= max_iters; ++k) {
+        auto one_sweep = [&]() {
             if (p.prec != 0)
                 sweep_tree_lp(r);
             else if (p.tree)
                 sweep_tree(r);
             else
                 sweep_generic(r);
+        };
+        // Graph replay: one sweep (and its fit) is captured from the stream once and replayed
+        // max_iters times; every node reads and writes the same workspace each sweep, and the fit
+        // lands in fits[k] through a device-side counter.  Needs a capturable (non-null) stream,
+        // no per-sweep host read (tol = 0) and no stage timers.
+        const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0;
+        GraphHold hold{s};
+        if (graphs) {
+            TK_HIP(tk_set_int(p.shifts + 3, 1, s));
+            TK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            try {
+                one_sweep();
+                core_norm_and_fit(r, p.scal + 4);
+                TK_HIP(tk_fit_push(p.scal + 4, p.shifts + 3, p.fits, s));
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(s, &g2);
+                if (g2) (void)hipGraphDestroy(g2);
+                (void)hipGetLastError();
+                throw;
+            }
+            TK_HIP(hipStreamEndCapture(s, &hold.graph));
+            TK_HIP(hipGraphInstantiate(&hold.exec, hold.graph, nullptr, nullptr, 0));
+            for (int k = 1; k <= max_iters; ++k) TK_HIP(hipGraphLaunch(hold.exec, s));
+            done = max_iters;
+        }
+        for (int k = 1; k <= max_iters && !graphs; ++k) {
+            one_sweep();
             sweep_fit(p.fits + k);
             done = k;
             if (tol > 0.0) {

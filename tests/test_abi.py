@@ -90,7 +90,7 @@ def test_server_without_gpu_and_null_arguments():
     lib = _lib.lib()
     o = _lib.ServerOptions()
     lib.tucker_default_server_options(C.byref(o))
-    assert o.slots == 4 and o.hbm_budget_bytes == 0 and o.init_iters == 20
+    assert o.slots == 4 and o.hbm_budget_bytes == 0 and o.init_iters == 20 and o.use_graphs == 1
     assert lib.tucker_server_create(None, None) == _lib.ERR_INVALID_ARG
     bad = _lib.ServerOptions()
     lib.tucker_default_server_options(C.byref(bad))
