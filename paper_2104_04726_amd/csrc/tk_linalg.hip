@@ -13,6 +13,7 @@
 // jacobi_eig: cyclic two-sided Jacobi (Golub & Van Loan, Alg. 8.4.3, with the parallel
 //   round-robin ordering) on a symmetric matrix of order <= 64 held in LDS.
 #include <algorithm>
+#include <utility>
 
 #include "tk_common.h"
 
@@ -171,15 +172,9 @@ __device__ void tile_gemm(double* C, const double* A, const double* B, bool tran
     __syncthreads();
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---- 64 x 64 tile factorisation and inversion, blocked by 16: the sequential parts are 16 x 16
-// problems solved inside one wave's registers (row r in lane r, column entries broadcast with
-// readlane, no barriers); the rest is parallel over the workgroup with a barrier per phase.
+// problems solved inside one wave's registers (row r in lane r, column entries broadcast across
+// lanes, no barriers); the rest is parallel over the workgroup with a barrier per phase.
 constexpr int SB = 16;   // inner block
 static_assert(TB == 64, "blocked tile kernels assume 64 x 64 tiles");
 
@@ -195,91 +190,107 @@ __device__ __forceinline__ double rcp_nr(double d) {
     return y;
 }
 
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-    const unsigned long long b = __double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+// ---- 16 x 16 diagonal blocks in one wave.  Lane r holds row r of the block (a[j] = A_rj) and
+// column r of its inverse (x[i] = X_ir); the four 16-lane rows of the wave repeat the same problem.
+// Column entries are broadcast within each 16-lane row with DPP row_newbcast, one instruction per
+// double.  A broadcast must run with every lane of the row active (a masked-off source lane reads
+// as zero), so it is never placed inside a lane-dependent branch.
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xF, 0xF, true);
 }
 
-// One wave: Cholesky of the 16 x 16 diagonal block at (o, o) of A (LDS, row stride TS), in place
-// (lower L, upper zeroed), and its inverse into Y (LDS 16 x 16, row stride SB).  L D L^T form: the
-// pivots are divided out once per column and the square roots applied at the end.
-__device__ void wave_potrf16(double* A, int o, double* Y, int* shifts) {
-    const int r = threadIdx.x & 63;
-    const bool act = r < SB;
-    double a[SB];
+// Elimination of column K (L D L^T form, pivot d = A_KK): for rows j > K,
+//   A_rj -= (A_rK / d) A_jK   and, for the unit-lower inverse, x_j -= (A_jK / d) x_K.
+template <int K, int... J>
+__device__ __forceinline__ void ldl_eliminate(double (&a)[SB], double (&x)[SB], double c, double ci, double t,
+                                              std::integer_sequence<int, J...>) {
+    ((a[K + 1 + J] = fma(-ci, row_bcast<K + 1 + J>(c), a[K + 1 + J]),
+      x[K + 1 + J] = fma(-row_bcast<K + 1 + J>(c), t, x[K + 1 + J])), ...);
+}
+
+template <int K>
+__device__ __forceinline__ void ldl_steps(double (&a)[SB], double (&x)[SB], double& dmine, int r, int& bad) {
+    if constexpr (K < SB) {
+        const double d = row_bcast<K>(a[K]);           // pivot of column K
+        if (r == K) dmine = d;
+        bad += (d > 1e-13) ? 0 : 1;
+        const double rinv = rcp_nr(safe_pivot(d));
+        const double c = a[K];
+        ldl_eliminate<K>(a, x, c, c * rinv, x[K] * rinv, std::make_integer_sequence<int, SB - 1 - K>{});
+        // the inverse columns feed nothing until the end; without this (empty) register constraint
+        // the compiler postpones their updates and parks every broadcast in spare registers
 #pragma unroll
-    for (int j = 0; j < SB; ++j) a[j] = act ? A[(o + r) * TS + o + j] : 0.0;
-    double dk[SB];
+        for (int j = K + 1; j < SB; ++j) asm volatile("" : "+v"(x[j]));
+        ldl_steps<K + 1>(a, x, dmine, r, bad);
+    }
+}
+
+// L = L~ D^1/2 (L_rj = A_rj / sqrt(d_j) below the diagonal, sqrt(d_r) on it, 0 above) and
+// L^-1 = D^-1/2 L~^-1 (row i of the inverse scaled by 1/sqrt(d_i)).
+template <int J>
+__device__ __forceinline__ void ldl_finish1(double (&a)[SB], double (&x)[SB], double sq, double rs, int r) {
+    const double b = row_bcast<J>(rs);
+    const double v = a[J] * b;
+    a[J] = (J < r) ? v : ((J == r) ? sq : 0.0);
+    x[J] *= b;
+}
+template <int... J>
+__device__ __forceinline__ void ldl_finish(double (&a)[SB], double (&x)[SB], double sq, double rs, int r,
+                                           std::integer_sequence<int, J...>) {
+    (ldl_finish1<J>(a, x, sq, rs, r), ...);
+}
+
+// One wave (all 64 lanes active): Cholesky of the 16 x 16 diagonal block at (o, o) of A (LDS, row
+// stride TS), in place (lower L, upper zeroed), and L^-1 into X (LDS, row stride ldx, zeros above
+// the diagonal).  Pivots <= 1e-13 are replaced by 1e-13 and counted in *shifts.
+__device__ void wave_potrf16(double* A, int o, double* X, int ldx, int* shifts) {
+    const int lane = threadIdx.x & 63, r = lane & 15;
+    double a[SB], x[SB];
 #pragma unroll
-    for (int k = 0; k < SB; ++k) {
-        const double d = readlane_f64(a[k], k);          // current pivot
-        dk[k] = d;
-        const double c = a[k];                           // unscaled column entry of this row
-        const double ci = c * rcp_nr(safe_pivot(d));
+    for (int j = 0; j < SB; ++j) {
+        a[j] = A[(o + r) * TS + o + j];
+        x[j] = (j == r) ? 1.0 : 0.0;
+    }
+    double dmine = 1.0;
+    int bad = 0;
+    ldl_steps<0>(a, x, dmine, r, bad);
+    const double sq = sqrt(safe_pivot(dmine));
+    const double rs = rcp_nr(sq);
+    ldl_finish(a, x, sq, rs, r, std::make_integer_sequence<int, SB>{});
+    if (lane < SB) {
 #pragma unroll
-        for (int j = k + 1; j < SB; ++j) {
-            const double cj = readlane_f64(c, j);
-            if (r >= j) a[j] -= ci * cj;
+        for (int j = 0; j < SB; ++j) {
+            A[(o + r) * TS + o + j] = a[j];
+            X[j * ldx + r] = x[j];
         }
     }
-    if (r == 0) {
-#pragma unroll
-        for (int k = 0; k < SB; ++k)
-            if (!(dk[k] > 1e-13)) atomicAdd(shifts, 1);
-    }
-    double sq[SB], rsq[SB];
-#pragma unroll
-    for (int k = 0; k < SB; ++k) {
-        sq[k] = sqrt(safe_pivot(dk[k]));
-        rsq[k] = rcp_nr(sq[k]);
-    }
-    // L_rj = a_rj / sqrt(d_j) (j < r), L_rr = sqrt(d_r)
-#pragma unroll
-    for (int j = 0; j < SB; ++j) a[j] = (j < r) ? a[j] * rsq[j] : ((j == r) ? sq[j] : 0.0);
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < SB; ++j) A[(o + r) * TS + o + j] = a[j];
-    }
-    // inverse: lane c computes column c of L^-1 by forward substitution (rows broadcast by readlane)
-    double x[SB];
-#pragma unroll
-    for (int i = 0; i < SB; ++i) {
-        double acc = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc -= readlane_f64(a[k], i) * x[k];
-        x[i] = (i < r) ? 0.0 : acc * rsq[i];
-    }
-    if (act) {
-#pragma unroll
-        for (int i = 0; i < SB; ++i) Y[i * SB + r] = x[i];
-    }
+    if (lane == 0 && bad) atomicAdd(shifts, bad);
 }
 
-// In-LDS Cholesky of the 64 x 64 tile A (lower; upper zeroed).  Right-looking over the four 16-wide
-// block columns: wave 0 factors the diagonal block and inverts it (Y = L_bb^-1); the block column
-// below, L_ib = A_ib Y^T, and the trailing update A_ij -= L_ib L_jb^T (i >= j, 16 x 16 tiles) run on
+// In-LDS Cholesky of the 64 x 64 tile A (lower; upper zeroed); the inverses of its four diagonal
+// 16 x 16 blocks go to the diagonal blocks of X (row stride TS).  Right-looking over the 16-wide
+// block columns: wave 0 factors and inverts the diagonal block; the block column below,
+// L_ib = A_ib L_bb^-T, and the trailing update A_ij -= L_ib L_jb^T (i >= j, 16 x 16 tiles) run on
 // the FP64 matrix cores, one 16 x 16 tile per wave.
-__device__ void tile_potrf(double* A, int* shifts) {
-    __shared__ double Y[SB * SB];
+__device__ void tile_potrf(double* A, double* X, int* shifts) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fk = lane >> 4;
     for (int b = 0; b < TB / SB; ++b) {
         const int o = b * SB;
-        if (tid < 64) wave_potrf16(A, o, Y, shifts);
+        if (tid < 64) wave_potrf16(A, o, X + o * TS + o, TS, shifts);
         __syncthreads();
         const int nt = (TB - o - SB) / SB;      // 16-row tiles below the diagonal block
         if (nt > 0) {
             if (wave < nt) {
-                // L_ic = sum_k A_ik Y_ck: A fragment (row fr, k), B fragment (k, column fr) = Y[fr][k]
+                // L_ic = sum_k A_ik Y_ck (Y = L_bb^-1): A fragment (row fr, k), B fragment (k, column fr) = Y[fr][k]
                 const int r0 = o + SB + SB * wave;
                 f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int st = 0; st < SB / 4; ++st) {
                     const int k = 4 * st + fk;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(r0 + fr) * TS + o + k], Y[fr * SB + k], acc, 0, 0,
-                                                               0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(r0 + fr) * TS + o + k], X[(o + fr) * TS + o + k],
+                                                               acc, 0, 0, 0);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) A[(r0 + fk + 4 * v) * TS + o + fr] = acc[v];
@@ -312,42 +323,16 @@ __device__ void tile_potrf(double* A, int* shifts) {
     __syncthreads();
 }
 
-// Inverse of the lower-triangular 64 x 64 tile L (LDS) into X (LDS): the four diagonal 16 x 16
-// inverses by four waves in parallel, then block forward substitution over the block rows:
-// X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj.
-__device__ void wave_trtri16(const double* L, int o, double* X) {
-    const int c = threadIdx.x & 63;
-    double rd[SB];
-#pragma unroll
-    for (int i = 0; i < SB; ++i) rd[i] = rcp_nr(L[(o + i) * TS + o + i]);
-    double x[SB];
-#pragma unroll
-    for (int i = 0; i < SB; ++i) {
-        double acc = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc -= L[(o + i) * TS + o + k] * x[k];
-        x[i] = (i < c) ? 0.0 : acc * rd[i];
-    }
-    if (c < SB) {
-#pragma unroll
-        for (int i = 0; i < SB; ++i) X[(o + i) * TS + o + c] = x[i];
-    }
-}
-
+// Inverse of the lower-triangular 64 x 64 tile L (LDS) into X (LDS), given the inverses of the
+// diagonal 16 x 16 blocks in X and zeros above them: block forward substitution over the block
+// rows, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj, on the FP64 matrix cores.
 __device__ void tile_trtri(const double* L, double* X) {
     __shared__ double Tm[3 * SB * SB];
     const int tid = threadIdx.x;
-    for (int e = tid; e < TB * TB; e += blockDim.x) {
-        const int i = e / TB, j = e % TB;
-        X[i * TS + j] = 0.0;
-    }
-    __syncthreads();
-    wave_trtri16(L, (tid >> 6) * SB, X);     // wave w inverts diagonal block w
-    __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fk = lane >> 4;
     for (int bi = 1; bi < TB / SB; ++bi) {
-        // wave j < bi: T_j = sum_{k=j}^{bi-1} L_{bi,k} X_{k,j} on the matrix cores
+        // wave j < bi: T_j = sum_{k=j}^{bi-1} L_{bi,k} X_{k,j}
         if (wave < bi) {
             const int bj = wave;
             f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
@@ -426,7 +411,9 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             tile_gemm(At, Bt, (i != j) ? Ct : Bt, true, -1.0, 1.0);
         }
         if (i == j) {
-            tile_potrf(At, a.shifts);
+            for (int e = threadIdx.x; e < TB * TS; e += blockDim.x) Bt[e] = 0.0;
+            __syncthreads();
+            tile_potrf(At, Bt, a.shifts);
             tile_trtri(At, Bt);
             store_tile(a.W, a.n, j, j, At);
             store_tile(a.Tout, a.n, j, j, Bt);
