@@ -16,6 +16,7 @@
 //   * fit: ||X||^2 - ||G||^2 per sweep (FP64 sums), and at the end 1 - ||X - Xhat|| / ||X|| from the
 //     explicit residual, fused into the last expanding product.
 #include <algorithm>
+#include <atomic>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -178,7 +179,8 @@ int64_t chain_max(const Plan& p) {
     return mx;
 }
 
-constexpr int kGramTargetBlocks = 1024;
+constexpr int64_t kGramFallbackCapacity = 768;
+constexpr double kGramSplitOverheadK = 256.0;   // fixed cost of a workgroup, in k steps
 constexpr int kLpScaleBlocks = 256;
 constexpr int kRefineInner = 4;
 constexpr int kLpGramTargetBlocks = 512;
@@ -197,13 +199,42 @@ int64_t lp_gram_partials(int64_t s, int64_t K) {
     return ((K + ks - 1) / ks) * s * s;
 }
 
+// Workgroups of the FP64 Gram kernel that are resident on the device at once (CUs x occupancy),
+// queried once per process on the current device; 768 (256 CUs x 3) when no device answers.
+int64_t gram_capacity() {
+    static std::atomic<int64_t> cached{0};
+    int64_t c = cached.load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int dev = 0, cus = 0;
+    const int per = gram_f64_blocks_per_cu();
+    if (per > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        c = (int64_t)cus * per;
+    else
+        c = kGramFallbackCapacity;
+    cached.store(c, std::memory_order_relaxed);
+    return c;
+}
+
+// Split-K of the FP64 Gram (64 x 64 lower-triangle tiles): the count minimising
+// rounds x (K / splits + overhead), where a round is one set of resident workgroups, so that the
+// last round is not left mostly empty; ties go to fewer splits (less partial-sum traffic).
 int gram_splits(int64_t s, int64_t K) {
-    const int64_t t = (s + 63) / 64;       // lower-triangle 64 x 64 FP64 MFMA tiles
+    const int64_t t = (s + 63) / 64;
     const int64_t tiles = t * (t + 1) / 2;
-    int64_t sp = (kGramTargetBlocks + tiles - 1) / tiles;
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
-    sp = std::max<int64_t>(sp, 1);
-    return (int)std::min<int64_t>(sp, 64);
+    const int64_t cap = gram_capacity();
+    const int64_t maxsp = std::min<int64_t>(64, std::max<int64_t>(1, K / 256));
+    int64_t best = 1;
+    double best_cost = 0.0;
+    for (int64_t sp = 1; sp <= maxsp; ++sp) {
+        const int64_t rounds = (tiles * sp + cap - 1) / cap;
+        const double cost = (double)rounds * ((double)K / (double)sp + kGramSplitOverheadK);
+        if (sp == 1 || cost < best_cost * 0.999) {
+            best = sp;
+            best_cost = cost;
+        }
+    }
+    return (int)best;
 }
 
 void build_plan(Plan& p, Arena& a) {

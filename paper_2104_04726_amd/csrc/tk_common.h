@@ -53,6 +53,8 @@ hipError_t gemm_f32(const GemmArgs& g, Orient oa, Orient ob, Epilogue epi, bool 
 // fp64 MFMA GEMM; a_is_f32/b_is_f32 select float operands converted to double on load
 hipError_t gemm_f64(const GemmArgs& g, Orient oa, Orient ob, Epilogue epi, bool a_is_f32,
                     bool b_is_f32, hipStream_t s);
+// workgroups of the FP64 Gram kernel (FP32 operands, both k-contiguous) resident per CU (0 if unknown)
+int gram_f64_blocks_per_cu();
 // number of blocks gemm_* launches for these arguments (for EPI_RESID partial sizing)
 int64_t gemm_grid_blocks(const GemmArgs& g, bool f64);
 

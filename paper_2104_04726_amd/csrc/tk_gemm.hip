@@ -564,4 +564,12 @@ hipError_t gemm_f64(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, boo
     return by_orient<double, double, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
 }
 
+int gram_f64_blocks_per_cu() {
+    int per = 0;
+    const void* k = reinterpret_cast<const void*>(&gemm_kernel<double, float, float, MK, MK, EPI_STORE, false, 64, 64,
+                                                               TK_F64_BK, 4>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, 0) != hipSuccess) return 0;
+    return per;
+}
+
 }  // namespace tk
