@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
         }
         red[tid] = off;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
             if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
         __syncthreads();
         red[tid] = tot;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = (int)blockDim.x / 2; w > 0; w >>= 1) {
             if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }

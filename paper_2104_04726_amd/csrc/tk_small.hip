@@ -374,70 +374,86 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
 constexpr int kFG_FPB = 64;
 __global__ __launch_bounds__(256) void fibre_gram_kernel(const float* __restrict__ in, int64_t A, int L,
                                                          double* __restrict__ partial) {
-    __shared__ float xs[kFG_FPB * 65];
-    const int npairs = L * (L + 1) / 2;
-    const int per = (npairs + blockDim.x - 1) / blockDim.x;   // <= 9 for L = 64
-    int pi[9], pj[9];
-    float acc[9];
-    for (int u = 0; u < 9; ++u) {
-        const int idx = threadIdx.x + u * blockDim.x;
-        int i = 0, j = 0;
-        if (u < per && idx < npairs) {
-            i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-            while ((i + 1) * (i + 2) / 2 <= idx) ++i;
-            while (i * (i + 1) / 2 > idx) --i;
-            j = idx - i * (i + 1) / 2;
-        } else {
-            i = -1;
-        }
-        pi[u] = i;
-        pj[u] = j;
-        acc[u] = 0.f;
-    }
-    double accd[9];
-    for (int u = 0; u < 9; ++u) accd[u] = 0.0;
+    // F = sum_f x_f x_f^T over the fibres x_f (rows of length L <= 64) of this block's chunks.
+    // Thread = one 3 x 3 tile (I, J), I >= J, of the lower triangle and one phase h of the fibres
+    // (fibres h, h + H, ... of each chunk); the H phase sums are added in phase order at the end.
+    constexpr int LDX = 67;                       // LDS row stride (L padded to a multiple of 3)
+    __shared__ float xs[kFG_FPB * LDX];
+    __shared__ double red[9 * 256];
+    const int t = threadIdx.x;
+    const int bL = (L + 2) / 3, Lp = 3 * bL;
+    const int P = bL * (bL + 1) / 2;
+    const int H = max(1, min(16, 256 / P));
+    const bool active = t < P * H;
+    const int pidx = active ? t % P : 0, ph = active ? t / P : 0;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+    const int J = pidx - I * (I + 1) / 2;
+    double acc[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) acc[u] = 0.0;
     const int64_t nchunks = (A + kFG_FPB - 1) / kFG_FPB;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t f0 = ch * kFG_FPB;
         const int nf = (int)((A - f0) < kFG_FPB ? (A - f0) : kFG_FPB);
         __syncthreads();
-        for (int g = threadIdx.x; g < nf * L; g += blockDim.x) xs[(g / L) * 65 + (g % L)] = in[f0 * L + g];
+        for (int g = t; g < kFG_FPB * Lp; g += blockDim.x) {
+            const int f = g / Lp, c = g - f * Lp;
+            xs[f * LDX + c] = (f < nf && c < L) ? in[(f0 + f) * L + c] : 0.f;
+        }
         __syncthreads();
-        for (int u = 0; u < 9; ++u) {
-            if (pi[u] < 0) continue;
-            double a = 0.0;
-            for (int f = 0; f < nf; ++f) a = fma((double)xs[f * 65 + pi[u]], (double)xs[f * 65 + pj[u]], a);
-            accd[u] += a;              // products of FP32 values are exact in FP64
+        if (active) {
+            const float* xa = xs + 3 * I;
+            const float* xb = xs + 3 * J;
+            for (int f = ph; f < nf; f += H) {
+                const double a0 = xa[f * LDX], a1 = xa[f * LDX + 1], a2 = xa[f * LDX + 2];
+                const double b0 = xb[f * LDX], b1 = xb[f * LDX + 1], b2 = xb[f * LDX + 2];
+                // products of FP32 values are exact in FP64
+                acc[0] = fma(a0, b0, acc[0]); acc[1] = fma(a0, b1, acc[1]); acc[2] = fma(a0, b2, acc[2]);
+                acc[3] = fma(a1, b0, acc[3]); acc[4] = fma(a1, b1, acc[4]); acc[5] = fma(a1, b2, acc[5]);
+                acc[6] = fma(a2, b0, acc[6]); acc[7] = fma(a2, b1, acc[7]); acc[8] = fma(a2, b2, acc[8]);
+            }
         }
     }
-    double* dst = partial + (int64_t)blockIdx.x * L * L;
-    for (int u = 0; u < 9; ++u) {
-        if (pi[u] < 0) continue;
-        dst[pi[u] * L + pj[u]] = accd[u];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) red[u * 256 + t] = acc[u];
+    __syncthreads();
+    if (t < P) {
+        double* dst = partial + (int64_t)blockIdx.x * L * L;
+        for (int u = 0; u < 9; ++u) {
+            double v = 0.0;
+            for (int h = 0; h < H; ++h) v += red[u * 256 + h * P + t];
+            const int i = 3 * I + u / 3, j = 3 * J + u % 3;
+            if (i < L && j <= i) dst[i * L + j] = v;
+        }
     }
-    (void)acc;
 }
 
+// F (symmetric) = sum over the nblocks partial lower triangles.  A team of 32 lanes per entry:
+// lane l adds partials l, l + 32, ... in order, then a fixed butterfly adds the 32 lane sums, so
+// the result does not depend on timing.
 __global__ __launch_bounds__(256) void fibre_gram_reduce(const double* __restrict__ partial, int nblocks,
                                                          int L, double* __restrict__ F) {
     const int npairs = L * (L + 1) / 2;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < npairs; idx += gridDim.x * blockDim.x) {
-        int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = (int)(gt >> 5), l = (int)(gt & 31);
+    const bool valid = idx < npairs;
+    int i = 0, j = 0;
+    if (valid) {
+        i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
         while ((i + 1) * (i + 2) / 2 <= idx) ++i;
         while (i * (i + 1) / 2 > idx) --i;
-        const int j = idx - i * (i + 1) / 2;
-        // eight loads in flight, summed in block order (same result as a plain loop)
-        double s = 0.0;
+        j = idx - i * (i + 1) / 2;
+    }
+    double s = 0.0;
+    if (valid) {
         const int64_t st = (int64_t)L * L, off = (int64_t)i * L + j;
-        int b = 0;
-        for (; b + 8 <= nblocks; b += 8) {
-            double v[8];
+#pragma unroll 4
+        for (int b = l; b < nblocks; b += 32) s += partial[(int64_t)b * st + off];
+    }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(b + u) * st + off];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; b < nblocks; ++b) s += partial[(int64_t)b * st + off];
+    for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+    if (valid && l == 0) {
         F[i * L + j] = s;
         F[j * L + i] = s;
     }
@@ -736,8 +752,8 @@ hipError_t fibre_gram(const float* in, int64_t A, int L, double* partial, int nb
     hipLaunchKernelGGL(fibre_gram_kernel, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fibre_gram_reduce, dim3(grid_for(L * (L + 1) / 2, 64)), dim3(256), 0, s, partial,
-                       nblocks, L, F);
+    hipLaunchKernelGGL(fibre_gram_reduce, dim3((unsigned)((L * (L + 1) / 2 * 32 + 255) / 256)), dim3(256), 0, s,
+                       partial, nblocks, L, F);
     return hipGetLastError();
 }
 
@@ -754,8 +770,8 @@ hipError_t small_gram(const float* in, int64_t A, int64_t sdim, int64_t B, doubl
     hipLaunchKernelGGL(small_gram_kernel, dim3(nblocks), dim3(256), 0, s, in, A, sdim, B, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fibre_gram_reduce, dim3(grid_for(sdim * (sdim + 1) / 2, 64)), dim3(256), 0, s, partial,
-                       nblocks, (int)sdim, S);
+    hipLaunchKernelGGL(fibre_gram_reduce, dim3((unsigned)((sdim * (sdim + 1) / 2 * 32 + 255) / 256)), dim3(256), 0,
+                       s, partial, nblocks, (int)sdim, S);
     return hipGetLastError();
 }
 
