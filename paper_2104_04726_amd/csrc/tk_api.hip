@@ -125,7 +125,9 @@ struct Plan {
     double* Wpart = nullptr;
     int64_t Wpart_elems = 0;
     double* Tm = nullptr;
-    void* chol_ws = nullptr;
+    void* chol_ws = nullptr;     // task-graph counters of the Cholesky (zero between calls)
+    double* chol_dsc = nullptr;
+    int64_t chol_cap = 0;        // largest order the counters are sized for
     double* F = nullptr;
     double* Fpart = nullptr;
     // norms and fits
@@ -303,7 +305,9 @@ void build_plan(Plan& p, Arena& a) {
     p.Wpart_elems = std::max<int64_t>(16 * Rm * Rm, 8 * sR);
     p.Wpart = a.take<double>(p.Wpart_elems);
     p.Tm = a.take<double>(Rm * Rm);
-    p.chol_ws = a.take<char>(chol_counter_ints(Rm) * 4 + 64 + Rm * 8);
+    p.chol_ws = a.take<int>(chol_counter_ints(Rm));
+    p.chol_dsc = a.take<double>(Rm);
+    p.chol_cap = Rm;
     if (!p.tree) {
         p.F = a.take<double>(64 * 64);
         p.Fpart = a.take<double>(64 * 64 * 64);
@@ -313,7 +317,7 @@ void build_plan(Plan& p, Arena& a) {
     p.rpart = a.take<double>(p.rpart_elems);
     p.scal = a.take<double>(8);
     p.fits = a.take<double>(p.max_iters + p.refine + 2);
-    p.shifts = a.take<int>(4);
+    p.shifts = a.take<int>(8);
     if (!p.tree) p.Xh = (p.kind[0] == LARGE && p.s[0] > kSmallMode) ? nullptr : a.take<float>(Xn);
 }
 
@@ -497,6 +501,14 @@ void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, doub
 }
 
 // Q = A T^T (A rows x cols float/double, T cols x cols lower-triangular fp64) -> Q fp64
+// Every call that factors starts with zeroed counters: p.shifts (pivot shifts, second-pass count,
+// the second-pass flag, the fit counter, the orthogonality-check ticket) and the Cholesky task-graph
+// counters, which each factorisation leaves zeroed for the next.
+void reset_counters(Run& r) {
+    TK_HIP(fill_zero(r.p.shifts, 8 * (int64_t)sizeof(int), r.st));
+    if (r.p.chol_ws) TK_HIP(fill_zero(r.p.chol_ws, chol_counter_ints(r.p.chol_cap) * (int64_t)sizeof(int), r.st));
+}
+
 void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, const double* Tm, double* Q,
                const int* run_if = nullptr) {
     GemmArgs g{};
@@ -532,21 +544,22 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     const double shift = cold ? 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols : 0.0;
     // pass 1: Z -> Q1
     gram_tn64(r, Z, z32, rows, cols, p.W);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+    TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
     apply_tri(r, Z, z32, rows, cols, p.Tm, p.Q1);
     gram_tn64(r, p.Q1, false, rows, cols, p.W);
     if (!cold) {
         // pass 2 only where needed: need = p.shifts[2], counted in p.shifts[1]
         int* need = p.shifts + 2;
-        TK_HIP(orth_check(p.W, cols, r.orth_tol, p.red, need, p.shifts + 1, r.st));
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st, need));
+        TK_HIP(orth_check(p.W, cols, r.orth_tol, p.red, need, p.shifts + 1, p.shifts + 4, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st, need));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64, need);
-        TK_HIP(copy_unless(need, p.Q1, U64, rows * cols, r.st));
+        TK_HIP(finish_factor(need, p.Q1, U64, U32, rows * cols, r.st));
+        return;
     } else {
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
         gram_tn64(r, U64, false, rows, cols, p.W);
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.shifts, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
         apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
         TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
     }
@@ -1291,7 +1304,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps);
         bind(ctx, p);
         const hipStream_t s = r.st;
-        TK_HIP(fill_zero(p.shifts, 16, s));
+        reset_counters(r);
         TK_HIP(hipEventRecord(ctx->ev[0], s));
         const int64_t Xn = prod(p.s, 0, p.N);
         TK_HIP(sumsq_f32(tensor, Xn, p.red, kSumsqBlocks, p.scal + 0, s));
@@ -1609,13 +1622,15 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
             p.Wpart_elems = 16 * cols * cols;
             p.Wpart = a.take<double>(p.Wpart_elems);
             p.Tm = a.take<double>(cols * cols);
-            p.chol_ws = a.take<char>(chol_counter_ints(cols) * 4 + 64 + cols * 8);
+            p.chol_ws = a.take<int>(chol_counter_ints(cols));
+            p.chol_dsc = a.take<double>(cols);
+            p.chol_cap = cols;
             p.Q1 = a.take<double>(rows * cols);
-            p.shifts = a.take<int>(4);
+            p.shifts = a.take<int>(8);
             p.red = a.take<double>(kSumsqBlocks);
             U64 = a.take<double>(rows * cols);
         });
-        TK_HIP(fill_zero(p.shifts, 16, r.st));
+        reset_counters(r);
         orthonormalize(r, Z, true, rows, cols, U64, Q, true);
     });
 }
@@ -1639,16 +1654,19 @@ tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, doubl
     if (!W || !T || n < 1) return TUCKER_ERR_INVALID_ARG;
     return guarded(ctx, [&]() {
         double* Wc = nullptr;
-        void* cw = nullptr;
+        double* dsc = nullptr;
+        int* cw = nullptr;
         int* shifts = nullptr;
         with_scratch(ctx, [&](Arena& a) {
             Wc = a.take<double>(n * n);
-            cw = a.take<char>(chol_counter_ints(n) * 4 + 64 + n * 8);
+            cw = a.take<int>(chol_counter_ints(n));
+            dsc = a.take<double>(n);
             shifts = a.take<int>(4);
         });
         TK_HIP(fill_zero(shifts, 16, ctx->stream));
+        TK_HIP(fill_zero(cw, chol_counter_ints(n) * (int64_t)sizeof(int), ctx->stream));
         TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, (int*)cw, shifts, ctx->stream));
+        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, cw, dsc, shifts, ctx->stream));
         int sh = 0;
         TK_HIP(hipMemcpyAsync(&sh, shifts, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         TK_HIP(hipStreamSynchronize(ctx->stream));

@@ -121,20 +121,23 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // ---------------------------------------------------------------------------------------
 // Dense linear algebra (tk_linalg.hip)
 // ---------------------------------------------------------------------------------------
-// In place on W (n x n fp64, lower triangle read): column-scaled Cholesky W~ + shift I = L L^T
-// (W~ = D^-1 W D^-1) by a tiled task graph, then T = L^-1 D^-1 (lower triangular) to Tout.
-// counters: int workspace of chol_counter_ints(n) entries (zeroed by the call).
+// Column-scaled Cholesky W~ + shift I = L L^T of W (n x n fp64, lower triangle read; W~ =
+// D^-1 W D^-1, D = sqrt(diag W) when scale) by a tiled task graph, then T = L^-1 D^-1 (lower
+// triangular) to Tout.  W's off-diagonal tiles are overwritten by L; its diagonal tiles are kept.
+// counters: chol_counter_ints(n) ints that must be zero on entry; they are zero again when the
+// call's kernels have finished.  dsc: n doubles of scratch (the diagonal scale).
 // shifts: int counter incremented for every pivot that needed the shifted fallback.
 // run_if (nullable): every kernel of the call returns at once when *run_if == 0.
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           int* shifts, hipStream_t s, const int* run_if = nullptr);
-// need[0] = 1 (and ++count[0]) when max_ij |W_ij - delta_ij| > tol, else 0 (n x n FP64).
-// partial: orth_check_partials() doubles of scratch.
-hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count,
+                           double* dsc, int* shifts, hipStream_t s, const int* run_if = nullptr);
+// need[0] = 1 (and ++count[0]) when max_ij |W_ij - delta_ij| > tol, else 0 (n x n FP64), in one
+// launch.  partial: orth_check_partials() doubles of scratch; sync: an int that is zero on entry
+// (and zero again afterwards).
+hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count, int* sync,
                       hipStream_t s);
 int orth_check_partials();
-// dst = src (n doubles) when *need == 0
-hipError_t copy_unless(const int* need, const double* src, double* dst, int64_t n, hipStream_t s);
+// *need != 0: U32 = (float)U64; else U64 = Q1 and U32 = (float)Q1 (n values)
+hipError_t finish_factor(const int* need, const double* Q1, double* U64, float* U32, int64_t n, hipStream_t s);
 int64_t chol_counter_ints(int64_t n);
 
 // Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading

@@ -33,7 +33,8 @@ struct CholArgs {
     int64_t n;
     int T;
     double shift;          // added to the diagonal of the scaled matrix
-    const double* dsc;     // 1/sqrt(W_ii) (or 1)
+    bool scale;            // scale by D^-1 on both sides (D = sqrt(diag W)); else D = I
+    double* dsc;           // out: 1/sqrt(W_ii) (or 1), written by the diagonal tasks
     double* Tout;
     int* ticket;
     int* flagL;
@@ -85,12 +86,12 @@ __device__ void release_flag(int* f) {
 }
 
 // tile (ti,tj) of an n x n row-major matrix -> LDS t; out-of-range -> 0 (or 1 on the diagonal
-// when pad_diag), optionally scaled by dsc[r] dsc[c] and shifted on the diagonal.  Every thread
+// when pad_diag), optionally scaled by dr[r] dc[c] (LDS, local row / column) and shifted on the diagonal.  Every thread
 // issues all of its TB*TB/256 coherent loads before the first use, so their latencies overlap.
 constexpr int kTileVals = TB * TB / 256;
 
-__device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dsc,
-                          bool pad_diag, double shift = 0.0) {
+__device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dr,
+                          const double* dc, bool pad_diag, double shift = 0.0) {
     double v[kTileVals];
 #pragma unroll
     for (int u = 0; u < kTileVals; ++u) {
@@ -108,7 +109,7 @@ __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t,
         double x;
         if (gr < n && gc < n) {
             x = v[u];
-            if (dsc) x *= dsc[gr] * dsc[gc];
+            if (dr) x *= dr[r] * dc[c];
             if (gr == gc) x += shift;
         } else {
             x = (pad_diag && gr == gc) ? 1.0 : 0.0;
@@ -364,22 +365,6 @@ __device__ void tile_trtri(const double* L, double* X) {
     }
 }
 
-__global__ __launch_bounds__(256) void chol_prologue(const double* W, int64_t n, bool scale, double* dsc,
-                                                    int* shifts, const int* run_if) {
-    if (run_if && *run_if == 0) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double d = W[i * n + i];
-        if (!scale) {
-            dsc[i] = 1.0;
-        } else if (d > 0.0) {
-            dsc[i] = 1.0 / sqrt(d);
-        } else {
-            dsc[i] = 1.0;
-            atomicAdd(shifts, 1);
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
     __shared__ double At[TB * TS], Bt[TB * TS], Ct[TB * TS];
     __shared__ int task_s;
@@ -401,12 +386,32 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             ++j;
         }
         const int i = j + rem;
-        load_tile(a.W, a.n, i, j, At, a.dsc, i == j, i == j ? a.shift : 0.0);
+        // D^-1 for the rows of tile i and the columns of tile j, from the diagonal of W (the
+        // diagonal tiles of W are never overwritten: L_jj is not stored back)
+        __shared__ double dr[TB], dc[TB];
+        if (threadIdx.x < 2 * TB) {
+            const int l = threadIdx.x % TB;
+            const int64_t g = (int64_t)(threadIdx.x < TB ? i : j) * TB + l;
+            double v = 1.0;
+            if (g < a.n && a.scale) {
+                const double d = a.W[g * a.n + g];
+                v = (d > 0.0) ? 1.0 / sqrt(d) : 1.0;
+                if (i == j && threadIdx.x < TB) {
+                    a.dsc[g] = v;
+                    if (!(d > 0.0)) atomicAdd(a.shifts, 1);
+                }
+            } else if (g < a.n && i == j && threadIdx.x < TB) {
+                a.dsc[g] = 1.0;
+            }
+            (threadIdx.x < TB ? dr : dc)[l] = v;
+        }
+        __syncthreads();
+        load_tile(a.W, a.n, i, j, At, dr, dc, i == j, i == j ? a.shift : 0.0);
         __syncthreads();   // the whole tile is in LDS before wave 0 may factor it (j == 0)
         for (int k = 0; k < j; ++k) {
             wait_flags(fL(i, k), fL(j, k), a.err);
-            load_tile(a.W, a.n, i, k, Bt, nullptr, false);
-            if (i != j) load_tile(a.W, a.n, j, k, Ct, nullptr, false);
+            load_tile(a.W, a.n, i, k, Bt, nullptr, nullptr, false);
+            if (i != j) load_tile(a.W, a.n, j, k, Ct, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(At, Bt, (i != j) ? Ct : Bt, true, -1.0, 1.0);
         }
@@ -415,8 +420,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             __syncthreads();
             tile_potrf(At, Bt, a.shifts);
             tile_trtri(At, Bt);
-            store_tile(a.W, a.n, j, j, At);
-            store_tile(a.Tout, a.n, j, j, Bt);
+            store_tile(a.Tout, a.n, j, j, Bt);     // L_jj itself is not needed by any later task
             stores_done();
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             }
         } else {
             wait_flags(fL(j, j), nullptr, a.err);
-            load_tile(a.Tout, a.n, j, j, Bt, nullptr, false);
+            load_tile(a.Tout, a.n, j, j, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Ct, At, Bt, true, 1.0, 0.0);       // L_ij = A_ij Linv_jj^T
             store_tile(a.W, a.n, i, j, Ct);
@@ -442,13 +446,13 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
         __syncthreads();
         for (int k = j; k < i; ++k) {
             wait_flags(fL(i, k), fI(k, j), a.err);
-            load_tile(a.W, a.n, i, k, At, nullptr, false);
-            load_tile(a.Tout, a.n, k, j, Bt, nullptr, false);
+            load_tile(a.W, a.n, i, k, At, nullptr, nullptr, false);
+            load_tile(a.Tout, a.n, k, j, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Ct, At, Bt, false, 1.0, 1.0);       // acc += L_ik Linv_kj
         }
         wait_flags(fI(i, i), nullptr, a.err);
-        load_tile(a.Tout, a.n, i, i, At, nullptr, false);
+        load_tile(a.Tout, a.n, i, i, At, nullptr, nullptr, false);
         __syncthreads();
         tile_gemm(Bt, At, Ct, false, -1.0, 0.0);          // Linv_ij = -Linv_ii acc
         store_tile(a.Tout, a.n, i, j, Bt);
@@ -456,15 +460,19 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
     }
 }
 
-// a timed-out wait of the task graph is reported through the shift counter (+1e6)
-__global__ void chol_report(const int* err, int* shifts, const int* run_if) {
+// T <- lower(T) * D^-1 (column scaling), upper triangle zeroed.  Block 0 also reports a timed-out
+// wait of the task graph through the shift counter (+1e6) and then clears the graph's counters for
+// the next call.
+__global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc, int* counters,
+                                                     int nctr, int* shifts, const int* run_if) {
     if (run_if && *run_if == 0) return;
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *err) atomicAdd(shifts, 1000000);
-}
-
-// T <- lower(T) * D^-1 (column scaling), upper triangle zeroed
-__global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc, const int* run_if) {
-    if (run_if && *run_if == 0) return;
+    if (blockIdx.x == 0) {
+        __shared__ int err;
+        if (threadIdx.x == 0) err = counters[1];
+        __syncthreads();
+        if (threadIdx.x == 0 && err) atomicAdd(shifts, 1000000);
+        for (int e = threadIdx.x; e < nctr; e += blockDim.x) counters[e] = 0;
+    }
     const int64_t total = n * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = e / n, c = e % n;
@@ -475,9 +483,13 @@ __global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, cons
 // Deviation of a Gram Q^T Q from the identity, max_ij |W_ij - delta_ij|: per-block maxima, then
 // one block folds them and writes need = (max > tol) (NaN counts as needed) and counts the passes.
 constexpr int kOrthBlocks = 128;
-__global__ __launch_bounds__(256) void orth_dev_kernel(const double* __restrict__ W, int64_t n,
-                                                       double* __restrict__ partial) {
+// max_ij |W_ij - delta_ij| > tol -> *need = 1 (and ++*count), else *need = 0, in one launch: each
+// block reduces its share, and the last block to finish (ticket in *sync, cleared afterwards) takes
+// the maximum of the block maxima, which does not depend on their order.
+__global__ __launch_bounds__(256) void orth_check_kernel(const double* __restrict__ W, int64_t n, double tol,
+                                                         double* partial, int* need, int* count, int* sync) {
     __shared__ double red[256];
+    __shared__ int last;
     double m = 0.0;
     const int64_t total = n * n;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
@@ -493,24 +505,35 @@ __global__ __launch_bounds__(256) void orth_dev_kernel(const double* __restrict_
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-__global__ void orth_need_kernel(const double* __restrict__ partial, int nb, double tol, int* need, int* count) {
-    if (threadIdx.x != 0) return;
-    double m = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        const double o = partial[b];
-        if (o > m || o != o) m = o;
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&partial[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int t = __hip_atomic_fetch_add(sync, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (t == (int)gridDim.x - 1);
     }
-    const int nd = !(m <= tol);
-    *need = nd;
-    if (nd && count) atomicAdd(count, 1);
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) {
+            const double o = __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (o > mx || o != o) mx = o;
+        }
+        const int nd = !(mx <= tol);
+        *need = nd;
+        if (nd && count) atomicAdd(count, 1);
+        __hip_atomic_store(sync, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
-__global__ __launch_bounds__(256) void copy_unless_kernel(const int* need, const double* __restrict__ src,
-                                                          double* __restrict__ dst, int64_t n) {
-    if (*need) return;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+// *need: the second pass ran and U64 holds its result -> U32 = U64; else U64 = U32 = Q1
+__global__ __launch_bounds__(256) void finish_factor_kernel(const int* need, const double* __restrict__ Q1,
+                                                            double* __restrict__ U64, float* __restrict__ U32,
+                                                            int64_t n) {
+    const bool second = *need != 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = second ? U64[i] : Q1[i];
+        if (!second) U64[i] = v;
+        U32[i] = (float)v;
+    }
 }
 
 // ---------------------------------------------------------------- Jacobi
@@ -637,43 +660,36 @@ int64_t chol_counter_ints(int64_t n) {
 }
 
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           int* shifts, hipStream_t s, const int* run_if) {
+                           double* dsc, int* shifts, hipStream_t s, const int* run_if) {
     if (n <= 0) return hipSuccess;
     const int T = (int)((n + TB - 1) / TB);
-    // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); dsc stored after Tout?  no:
-    // the diagonal scale lives in the n doubles right after the counters (8-byte aligned).
-    hipError_t e = fill_zero(counters, chol_counter_ints(n) * (int64_t)sizeof(int), s);
-    if (e != hipSuccess) return e;
-    double* dsc = (double*)(((uintptr_t)(counters + chol_counter_ints(n)) + 15) & ~(uintptr_t)15);
-    hipLaunchKernelGGL(chol_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, scale, dsc, shifts, run_if);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    CholArgs a{W, n, T, shift, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1, run_if};
+    // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); zero on entry, cleared again
+    // by the epilogue
+    const int nctr = (int)chol_counter_ints(n);
+    CholArgs a{W, n, T, shift, scale, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1,
+               run_if};
     hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T)), dim3(256), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(chol_report, dim3(1), dim3(64), 0, s, counters + 1, shifts, run_if);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int64_t total = n * n;
     hipLaunchKernelGGL(chol_epilogue, dim3((unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096)),
-                       dim3(256), 0, s, Tout, n, dsc, run_if);
+                       dim3(256), 0, s, Tout, n, dsc, counters, nctr, shifts, run_if);
     return hipGetLastError();
 }
 
 int orth_check_partials() { return kOrthBlocks; }
 
-hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count,
+hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count, int* sync,
                       hipStream_t s) {
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kOrthBlocks, (n * n + 255) / 256));
-    hipLaunchKernelGGL(orth_dev_kernel, dim3(nb), dim3(256), 0, s, W, n, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(orth_need_kernel, dim3(1), dim3(64), 0, s, partial, nb, tol, need, count);
+    hipLaunchKernelGGL(orth_check_kernel, dim3(nb), dim3(256), 0, s, W, n, tol, partial, need, count, sync);
     return hipGetLastError();
 }
 
-hipError_t copy_unless(const int* need, const double* src, double* dst, int64_t n, hipStream_t s) {
+hipError_t finish_factor(const int* need, const double* Q1, double* U64, float* U32, int64_t n, hipStream_t s) {
     const int64_t g = std::min<int64_t>(2048, (n + 255) / 256);
     if (g <= 0) return hipSuccess;
-    hipLaunchKernelGGL(copy_unless_kernel, dim3((unsigned)g), dim3(256), 0, s, need, src, dst, n);
+    hipLaunchKernelGGL(finish_factor_kernel, dim3((unsigned)g), dim3(256), 0, s, need, Q1, U64, U32, n);
     return hipGetLastError();
 }
 
