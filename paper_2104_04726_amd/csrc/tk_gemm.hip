@@ -71,8 +71,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int TN = BN / 32;
     typedef typename Mfma<T>::V V;
 
-    __shared__ __attribute__((aligned(16))) T As[ASZ];
-    __shared__ __attribute__((aligned(16))) T Bs[BSZ];
+    // FP32 tiles with scalar loads use two LDS stages (the next k-tile is stored into one while the
+    // other is multiplied, one barrier per k-tile); measured slower for the vector-load and FP64
+    // variants, which keep one stage (barrier, store, barrier)
+    constexpr bool DB = VEC == 0 && sizeof(T) == 4;
+    constexpr int NST = DB ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) T As2[NST * ASZ];
+    __shared__ __attribute__((aligned(16))) T Bs2[NST * BSZ];
+    T* As = As2;     // stage written by store_tiles
+    T* Bs = Bs2;
     // VEC: both operands k-major (KM) FP32 with 4-aligned contiguous column runs; each thread moves
     // 4 consecutive columns per row as one 16-byte load and one 16-byte LDS store
     // VECK: both operands k-contiguous (MK) FP32 data with 4-aligned k runs; each operand tile is 128
@@ -386,9 +393,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         load_tiles(kbeg);
         store_tiles();
         __syncthreads();
+        int stage = 0;
         for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             const bool more = (k0 + BK) < kend;
             if (more) load_tiles(k0 + BK);
+            const T* Ac = As2 + stage * ASZ;
+            const T* Bc = Bs2 + stage * BSZ;
 #pragma unroll
             for (int kk = 0; kk < BK / 4; ++kk) {
                 const int k = kk * 4 + fk;
@@ -396,12 +406,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const int m = wbm + i * 16 + fr;
-                    av[i] = (OA == KM) ? As[k * LDA + m] : As[m * LDA + k];
+                    av[i] = (OA == KM) ? Ac[k * LDA + m] : Ac[m * LDA + k];
                 }
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const int n = wbn + j * 16 + fr;
-                    bv[j] = (OB == KM) ? Bs[k * LDB + n] : Bs[n * LDB + k];
+                    bv[j] = (OB == KM) ? Bc[k * LDB + n] : Bc[n * LDB + k];
                 }
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
@@ -419,10 +429,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         acc[i][j] = V{0, 0, 0, 0};
                     }
             }
-            __syncthreads();
-            if (more) {
-                store_tiles();
+            if constexpr (DB) {
+                // the other stage was last read before the previous barrier: store into it, then
+                // one barrier makes it readable and frees this stage for the store after next
+                if (more) {
+                    stage ^= 1;
+                    As = As2 + stage * ASZ;
+                    Bs = Bs2 + stage * BSZ;
+                    store_tiles();
+                }
                 __syncthreads();
+            } else {
+                __syncthreads();
+                if (more) {
+                    store_tiles();
+                    __syncthreads();
+                }
             }
         }
     }
