@@ -86,10 +86,11 @@ typedef struct {
 typedef enum {
     TUCKER_STAGE_PASS_A = 0,     /* * T34 = X x3 U3^T x4 U4^T, the first full-tensor pass      */
     TUCKER_STAGE_TTM_Y1 = 1,     /* * Y1 = T34 x2 U2^T                                         */
-    TUCKER_STAGE_GRAM_1 = 2,     /* * mode-1 Gram product (split-K partials)                   */
+    TUCKER_STAGE_GRAM_1 = 2,     /*   mode-1 Gram product, or with one inner step the products  */
+                                 /*   W = Y1 x1 U1^T and Y1_(1) W_(1)^T (S U without forming S) */
     TUCKER_STAGE_OI_1 = 3,       /*   orthogonal iteration + CholeskyQR2 of mode 1             */
     TUCKER_STAGE_TTM_Y2 = 4,     /* * Y2 = T34 x1 U1^T                                         */
-    TUCKER_STAGE_GRAM_2 = 5,     /* * mode-2 Gram product                                      */
+    TUCKER_STAGE_GRAM_2 = 5,     /*   mode-2 Gram product, or the two products as for mode 1   */
     TUCKER_STAGE_OI_2 = 6,       /*   orthogonal iteration + CholeskyQR2 of mode 2             */
     TUCKER_STAGE_PASS_C1 = 7,    /* * T1 = X x1 U1^T, the second full-tensor pass              */
     TUCKER_STAGE_TTM_C2 = 8,     /* * T12 = T1 x2 U2^T                                         */

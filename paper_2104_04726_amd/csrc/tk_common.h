@@ -45,6 +45,7 @@ struct GemmArgs {
     int lower_only;     // enumerate only tiles with tile_m >= tile_n (Gram / SYRK)
     double* resid_partial;   // EPI_RESID: one double per block
     const int* run_if;       // nullable: the launch does nothing when *run_if == 0
+    int c_f32;               // FP64 kernels, EPI_STORE: write c as float (rounded once)
 };
 
 // fp32 MFMA GEMM (operands fp32, accumulation fp32; acc64 = FP64 accumulation across k-tiles)

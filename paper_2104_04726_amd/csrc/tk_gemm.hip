@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     static_assert(VEC != 2 || (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
                                BM * BK == 1024),
                   "8-byte vector loads need k-contiguous FP32 operands and 1024-element tiles");
-    static_assert(VEC != 4 || (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+    static_assert(VEC != 4 || (OA == KM && OB == KM && sizeof(TA) == 4 && sizeof(TB) == 4 &&
                            (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
                       (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
                        (BM * BK == 512 || BM * BK == 1024)),
@@ -356,14 +356,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             return;
         }
         if constexpr (VEC == 4 && OA == KM) {
+            if constexpr (sizeof(T) == 4) {
 #pragma unroll
-            for (int u = 0; u < EA / 4; ++u)
-                *(float4*)&As[(av_r0 + av_step * u) * LDA + 4 * av_c4] =
-                    make_float4(ra[4 * u], ra[4 * u + 1], ra[4 * u + 2], ra[4 * u + 3]);
+                for (int u = 0; u < EA / 4; ++u)
+                    *(float4*)&As[(av_r0 + av_step * u) * LDA + 4 * av_c4] =
+                        make_float4(ra[4 * u], ra[4 * u + 1], ra[4 * u + 2], ra[4 * u + 3]);
 #pragma unroll
-            for (int u = 0; u < EB / 4; ++u)
-                *(float4*)&Bs[(bv_r0 + bv_step * u) * LDB + 4 * bv_c4] =
-                    make_float4(rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]);
+                for (int u = 0; u < EB / 4; ++u)
+                    *(float4*)&Bs[(bv_r0 + bv_step * u) * LDB + 4 * bv_c4] =
+                        make_float4(rb[4 * u], rb[4 * u + 1], rb[4 * u + 2], rb[4 * u + 3]);
+            } else {
+                // FP64 tiles of FP32 data: the 4 converted values as two 16-byte LDS stores
+#pragma unroll
+                for (int u = 0; u < EA / 4; ++u) {
+                    double2* d = (double2*)&As[(av_r0 + av_step * u) * LDA + 4 * av_c4];
+                    d[0] = make_double2(ra[4 * u], ra[4 * u + 1]);
+                    d[1] = make_double2(ra[4 * u + 2], ra[4 * u + 3]);
+                }
+#pragma unroll
+                for (int u = 0; u < EB / 4; ++u) {
+                    double2* d = (double2*)&Bs[(bv_r0 + bv_step * u) * LDB + 4 * bv_c4];
+                    d[0] = make_double2(rb[4 * u], rb[4 * u + 1]);
+                    d[1] = make_double2(rb[4 * u + 2], rb[4 * u + 3]);
+                }
+            }
             return;
         }
 #pragma unroll
@@ -467,7 +483,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 const double val =
                     ACC64 ? acc64[ACC64 ? i : 0][ACC64 ? j : 0][ACC64 ? v : 0] : (double)acc[i][j][v];
                 T* dst = pc + m * g.c.ld + co;
-                if (EPI == EPI_STORE) {
+                if (EPI == EPI_STORE && sizeof(T) == 8 && g.c_f32) {
+                    ((float*)g.c.ptr)[(int64_t)blockIdx.z * g.c_zstride + m * g.c.ld + co] = (float)(g.alpha * val);
+                } else if (EPI == EPI_STORE) {
                     *dst = (T)(g.alpha * val);
                 } else if (EPI == EPI_ADD) {
                     *dst = (T)(g.alpha * val + (double)*dst);
@@ -511,14 +529,14 @@ template <typename T, typename TA, typename TB, int OA, int OB, int EPI, bool AC
 hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
     dim3 grid = grid_of<T, BM, BN>(g);
     if (grid.x == 0) return hipSuccess;
-    constexpr bool can_vec = (OA == KM && OB == KM && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+    constexpr bool can_vec = (OA == KM && OB == KM && sizeof(TA) == 4 && sizeof(TB) == 4 &&
                               (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0) ||
                              (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
                               (BM * BK == 512 || BM * BK == 1024));
     if constexpr (can_vec) {
-        // the 1024-element form advances one k position for both operands: same segment layout
-        const bool same_seg = !(OA == MK && BM * BK == 1024) ||
-                              (g.a.seg == g.b.seg && g.a.segstride == g.b.segstride);
+        // the 1024-element form advances one k position for both operands: equal segment lengths
+        // (each operand keeps its own segment stride)
+        const bool same_seg = !(OA == MK && BM * BK == 1024) || g.a.seg == g.b.seg;
         if (km_vec_ok(g.a) && km_vec_ok(g.b) && same_seg && (OA == KM || g.k_split % 4 == 0)) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 4>), grid, dim3(256), 0, s,
                                g);

@@ -145,6 +145,28 @@ def test_stack_matches_oracle(ctx, name):
     assert max(m["orth"]) <= 1e-5
 
 
+def test_stack_two_inner_steps_matches_oracle():
+    """Two orthogonal-iteration steps per update take the Gram path (S = Y Y^T formed, then S U);
+    one step takes the product path (Y (Y^T U)).  Both reach the oracle's stationary point."""
+    import paper_2104_04726_amd as tk
+    c = STACK_CONFIGS["stack_mini"]
+    x32 = make_stereo_stack(c["H"], c["W"], c["E"], c["colorspace"], c["seed"])
+    ranks, iters = c["ranks"], c["sweeps"]
+    ctx2 = tk.Context(0, inner_iters=2)
+    try:
+        _say("stack_mini, 2 inner steps")
+        g = _gpu(ctx2, x32, ranks, iters)
+    finally:
+        ctx2.close()
+    o = _ora(x32, ranks, iters)
+    m = oracle.compare(g, o)
+    sin_tol, recon_tol = _gap_bounds(o, ranks)
+    _say(f"  metrics {m}")
+    assert m["fit"] <= 1e-5 and m["core_norm"] <= 1e-5, m
+    assert m["recon"] <= recon_tol, (m, recon_tol)
+    assert max(m["orth"]) <= 1e-5
+
+
 # ------------------------------------------------------------------ API behaviour
 
 def test_resume_equals_longer_run(ctx):
