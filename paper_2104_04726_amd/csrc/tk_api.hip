@@ -541,6 +541,14 @@ constexpr double kOrthTolLowp = 1e-8;  // reduced-precision sweeps: far below th
 void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
                     bool cold) {
     Plan& p = r.p;
+    if (!cold && !U32) {
+        // an intermediate step of the cold start: one CholeskyQR pass gives a basis of span(Z),
+        // all that the next product S U needs; the last step delivers the orthonormal factor
+        gram_tn64(r, Z, z32, rows, cols, p.W);
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
+        apply_tri(r, Z, z32, rows, cols, p.Tm, U64);
+        return;
+    }
     const double u = std::ldexp(1.0, -53);
     const double shift = cold ? 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols : 0.0;
     // pass 1: Z -> Q1
@@ -597,7 +605,10 @@ void orth_iter(Run& r, int n, int q, bool cold) {
             g.c = plain(p.Z, R);
             TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
         }
-        orthonormalize(r, p.Z, false, s, R, p.U64[n], p.U32[n], cold && it < 2);
+        // cold start: shifted CholeskyQR3 for the first two steps, one pass for the intermediate
+        // ones (U32 = nullptr), the checked CholeskyQR2 for the last
+        const bool mid = cold && it >= 2 && it < q - 1;
+        orthonormalize(r, p.Z, false, s, R, p.U64[n], mid ? nullptr : p.U32[n], cold && it < 2);
     }
 }
 
