@@ -3,7 +3,9 @@
 // chol_inv_scaled: W~ = D^-1 W D^-1 (D = sqrt(diag W)) is factored W~ = L L^T and T = L^-1 D^-1 is
 //   produced, so that Q = Z T^T has orthonormal columns when W = Z^T Z (one CholeskyQR pass).
 //   The n x n problem is split into 64 x 64 tiles and run as one launch of a tiled task graph:
-//   factor tasks (i,j), i >= j, in column-major order, then inverse tasks (i,j), i > j.
+//   factor tasks in column-major order, then inverse tasks (i,j), i > j.  The diagonal task (j,j)
+//   also forms the sub-diagonal tile L(j,j-1) as soon as the inverse of L(j-1,j-1) is published
+//   and applies its update from LDS, so the critical path crosses one flag per column.
 //   Each workgroup claims the next task with an atomic ticket, so every task it waits for was
 //   claimed earlier by a running workgroup: the graph cannot deadlock whatever the residency.
 //   Waits are bounded spins; a timeout raises an error flag instead of hanging.
@@ -366,56 +368,81 @@ __device__ void tile_trtri(const double* L, double* X) {
 }
 
 __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
-    __shared__ double At[TB * TS], Bt[TB * TS], Ct[TB * TS];
+    __shared__ double At[TB * TS], Bt[TB * TS], Ct[TB * TS], Dt[TB * TS];
     __shared__ int task_s;
     if (a.run_if && *a.run_if == 0) return;
     if (threadIdx.x == 0) task_s = atomicAdd(a.ticket, 1);
     __syncthreads();
     const int task = task_s;
     const int T = a.T;
-    const int nf = T * (T + 1) / 2;
-    if (task >= T * T) return;
+    // factor tasks, column by column: the diagonal task (j, j) (which also forms the sub-diagonal
+    // tile L(j, j-1)), then (i, j) for i >= j + 2; then the inverse tasks
+    const int nf = T * (T + 1) / 2 - (T - 1);
+    if (task >= nf + T * (T - 1) / 2) return;
     auto fL = [&](int i, int j) { return a.flagL + i * T + j; };
     auto fI = [&](int i, int j) { return a.flagI + i * T + j; };
 
     if (task < nf) {
-        // column-major lower index -> (i, j)
         int j = 0, rem = task;
-        while (rem >= T - j) {
-            rem -= T - j;
+        while (rem >= ((j < T - 1) ? T - j - 1 : 1)) {
+            rem -= (j < T - 1) ? T - j - 1 : 1;
             ++j;
         }
-        const int i = j + rem;
-        // D^-1 for the rows of tile i and the columns of tile j, from the diagonal of W (the
-        // diagonal tiles of W are never overwritten: L_jj is not stored back)
-        __shared__ double dr[TB], dc[TB];
-        if (threadIdx.x < 2 * TB) {
-            const int l = threadIdx.x % TB;
-            const int64_t g = (int64_t)(threadIdx.x < TB ? i : j) * TB + l;
+        const int i = (rem == 0) ? j : j + 1 + rem;
+        const bool diag = i == j;
+        const bool sub = diag && j > 0;
+        // D^-1 for the rows of tile i, the columns of tile j and (sub) those of tile j - 1, from the
+        // diagonal of W (the diagonal tiles of W are never overwritten: L_jj is not stored back)
+        __shared__ double dr[TB], dc[TB], dp[TB];
+        if (threadIdx.x < 3 * TB) {
+            const int grp = threadIdx.x / TB, l = threadIdx.x % TB;
+            const int tile = grp == 0 ? i : (grp == 1 ? j : j - 1);
+            const int64_t g = (int64_t)tile * TB + l;
             double v = 1.0;
-            if (g < a.n && a.scale) {
+            if (tile >= 0 && g < a.n && a.scale) {
                 const double d = a.W[g * a.n + g];
                 v = (d > 0.0) ? 1.0 / sqrt(d) : 1.0;
-                if (i == j && threadIdx.x < TB) {
+                if (diag && grp == 0) {
                     a.dsc[g] = v;
                     if (!(d > 0.0)) atomicAdd(a.shifts, 1);
                 }
-            } else if (g < a.n && i == j && threadIdx.x < TB) {
+            } else if (tile >= 0 && g < a.n && diag && grp == 0) {
                 a.dsc[g] = 1.0;
             }
-            (threadIdx.x < TB ? dr : dc)[l] = v;
+            (grp == 0 ? dr : (grp == 1 ? dc : dp))[l] = v;
         }
         __syncthreads();
-        load_tile(a.W, a.n, i, j, At, dr, dc, i == j, i == j ? a.shift : 0.0);
+        load_tile(a.W, a.n, i, j, At, dr, dc, diag, diag ? a.shift : 0.0);
+        if (sub) load_tile(a.W, a.n, j, j - 1, Ct, dr, dp, false);
         __syncthreads();   // the whole tile is in LDS before wave 0 may factor it (j == 0)
-        for (int k = 0; k < j; ++k) {
-            wait_flags(fL(i, k), fL(j, k), a.err);
-            load_tile(a.W, a.n, i, k, Bt, nullptr, nullptr, false);
-            if (i != j) load_tile(a.W, a.n, j, k, Ct, nullptr, nullptr, false);
+        if (sub) {
+            // A_jj -= L_jk L_jk^T and A_j,j-1 -= L_jk L_j-1,k^T for k < j - 1
+            for (int k = 0; k < j - 1; ++k) {
+                wait_flags(fL(j, k), fL(j - 1, k), a.err);
+                load_tile(a.W, a.n, j, k, Bt, nullptr, nullptr, false);
+                load_tile(a.W, a.n, j - 1, k, Dt, nullptr, nullptr, false);
+                __syncthreads();
+                tile_gemm(At, Bt, Bt, true, -1.0, 1.0);
+                tile_gemm(Ct, Bt, Dt, true, -1.0, 1.0);
+            }
+            // L_j,j-1 = A_j,j-1 Linv_j-1^T, published at once; then A_jj -= L_j,j-1 L_j,j-1^T from LDS
+            wait_flags(fI(j - 1, j - 1), nullptr, a.err);
+            load_tile(a.Tout, a.n, j - 1, j - 1, Bt, nullptr, nullptr, false);
             __syncthreads();
-            tile_gemm(At, Bt, (i != j) ? Ct : Bt, true, -1.0, 1.0);
+            tile_gemm(Dt, Ct, Bt, true, 1.0, 0.0);
+            store_tile(a.W, a.n, j, j - 1, Dt);
+            release_flag(fL(j, j - 1));
+            tile_gemm(At, Dt, Dt, true, -1.0, 1.0);
+        } else {
+            for (int k = 0; k < j; ++k) {
+                wait_flags(fL(i, k), fL(j, k), a.err);
+                load_tile(a.W, a.n, i, k, Bt, nullptr, nullptr, false);
+                if (!diag) load_tile(a.W, a.n, j, k, Ct, nullptr, nullptr, false);
+                __syncthreads();
+                tile_gemm(At, Bt, diag ? Bt : Ct, true, -1.0, 1.0);
+            }
         }
-        if (i == j) {
+        if (diag) {
             for (int e = threadIdx.x; e < TB * TS; e += blockDim.x) Bt[e] = 0.0;
             __syncthreads();
             tile_potrf(At, Bt, a.shifts);
@@ -668,7 +695,7 @@ hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, doubl
     const int nctr = (int)chol_counter_ints(n);
     CholArgs a{W, n, T, shift, scale, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1,
                run_if};
-    hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T - T + 1)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = n * n;
