@@ -97,6 +97,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                        (BM * BK == 512 || BM * BK == 1024)),
                   "vector loads need whole float4 per thread");
     constexpr bool VK2 = VECK && BM * BK == 1024;   // every thread loads one vector of A and one of B
+    // D2: FP64 operands with 2-aligned contiguous runs (64 x 64 x 16 tiles): 16-byte loads of two
+    // doubles, two per operand per thread.  KM tile (16 k-rows x 64): row tid / 32 + 8 u, column
+    // pair tid % 32; MK tile (64 rows x 16 k): row tid / 8 + 32 u, k pair tid % 8.
+    constexpr bool D2 = VEC == 8;
+    static_assert(!D2 || (sizeof(T) == 8 && sizeof(TA) == 8 && sizeof(TB) == 8 && BM == 64 && BN == 64 && BK == 16),
+                  "two-double loads need FP64 operands and 64 x 64 x 16 tiles");
     if (g.run_if && *g.run_if == 0) return;
 
     const int tid = threadIdx.x;
@@ -202,6 +208,64 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
     T ra[EA], rb[EB];
 
+    // D2 coordinates: fixed column offset (KM) or incremental k position (MK) per operand
+    struct D2Op {
+        int64_t fix;     // KM: offset of the thread's column pair
+        bool colok;      // KM: the pair is inside the matrix
+        int64_t kq, kr;  // MK: segment and offset of the thread's k pair
+    };
+    D2Op d2o[2] = {{0, false, 0, 0}, {0, false, 0, 0}};
+    double2 d2v[2][2];
+    if constexpr (D2) {
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            const Desc& d = o ? g.b : g.a;
+            const int orient = o ? OB : OA;
+            const int64_t x0 = o ? n0 : m0, ext = o ? g.N : g.M;
+            if (orient == KM) {
+                const int64_t c = x0 + 2 * (tid % 32);
+                d2o[o].colok = c < ext;
+                d2o[o].fix = d2o[o].colok ? coloff(d, c) : 0;
+            } else {
+                const int64_t k = kbeg + 2 * (tid % 8);
+                d2o[o].kq = k / d.seg;
+                d2o[o].kr = k % d.seg;
+            }
+        }
+    }
+    auto d2_load = [&](int o, int64_t k0) {
+        const Desc& d = o ? g.b : g.a;
+        const int orient = o ? OB : OA;
+        const double* base = (const double*)d.ptr;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            double2 v = make_double2(0.0, 0.0);
+            if (orient == KM) {
+                const int64_t k = k0 + tid / 32 + 8 * u;
+                if (d2o[o].colok && k < kend) v = *(const double2*)(base + k * d.ld + d2o[o].fix);
+            } else {
+                const int64_t row = (o ? n0 : m0) + tid / 8 + 32 * u;
+                const int64_t k = k0 + 2 * (tid % 8);
+                if (row < (o ? g.N : g.M) && k < kend) {
+                    const double* src = base + row * d.ld + d2o[o].kq * d.segstride + d2o[o].kr;
+                    if (k + 2 <= kend) {
+                        v = *(const double2*)src;
+                    } else {
+                        v.x = src[0];
+                    }
+                }
+            }
+            d2v[o][u] = v;
+        }
+        if (orient == MK) {
+            d2o[o].kr += BK;
+            while (d2o[o].kr >= d.seg) {
+                d2o[o].kr -= d.seg;
+                ++d2o[o].kq;
+            }
+        }
+    };
+
     // MK operands: the column offset of k = kbeg + (thread's k column) advances by BK per k-tile;
     // one division at the start, increments afterwards (loads always advance tile by tile)
     struct KCol {
@@ -240,6 +304,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     };
     auto load_tiles = [&](int64_t k0) {
+        if constexpr (D2) {
+            d2_load(0, k0);
+            d2_load(1, k0);
+            return;
+        }
         if constexpr (VECK) {
             auto ld4 = [&](const Desc& d, int64_t rows, int64_t row, int64_t k) {
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -327,6 +396,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     };
     auto store_tiles = [&]() {
+        if constexpr (D2) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                T* dst = o ? Bs : As;
+                const int ld = o ? LDB : LDA;
+                const int orient = o ? OB : OA;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int idx = (orient == KM) ? (tid / 32 + 8 * u) * ld + 2 * (tid % 32)
+                                                   : (tid / 8 + 32 * u) * ld + 2 * (tid % 8);
+                    *(double2*)&dst[idx] = d2v[o][u];
+                }
+            }
+            return;
+        }
         if constexpr (VECK) {
             T* dst = (vk_half ? Bs : As) + vk_row * (vk_half ? LDB : LDA) + 4 * vk_k4;
             dst[0] = (T)vk_reg.x;
@@ -552,6 +636,19 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
         };
         if (ok2(g.a) && ok2(g.b) && g.a.seg == g.b.seg && g.a.segstride == g.b.segstride && g.k_split % 2 == 0) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 2>), grid, dim3(256), 0, s,
+                               g);
+            return hipGetLastError();
+        }
+    }
+    constexpr bool can_d2 = sizeof(T) == 8 && sizeof(TA) == 8 && sizeof(TB) == 8 && BM == 64 && BN == 64 && BK == 16;
+    if constexpr (can_d2) {
+        // 16-byte loads: runs of the contiguous index are 2-aligned and (KM) the extent is even
+        auto okd = [](const Desc& d, int orient, int64_t ext) {
+            const bool segok = d.seg >= (int64_t(1) << 61) || (d.seg % 2 == 0 && d.segstride % 2 == 0);
+            return segok && d.ld % 2 == 0 && (((uintptr_t)d.ptr) & 15) == 0 && (orient == MK || ext % 2 == 0);
+        };
+        if (okd(g.a, OA, g.M) && okd(g.b, OB, g.N) && g.k_split % 2 == 0) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 8>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
         }
