@@ -109,6 +109,8 @@ struct Plan {
     int64_t Pf_elems = 0;
 
     float* U32[TUCKER_MAX_ORDER]{};
+    double* Vsm[TUCKER_MAX_ORDER]{};    // small modes: the whole eigenvector basis of the last update
+    bool vsm_valid[TUCKER_MAX_ORDER]{};
     double* U64[TUCKER_MAX_ORDER]{};
     // tree buffers
     float *T34 = nullptr, *Y0 = nullptr, *Y1 = nullptr, *T1 = nullptr, *T12 = nullptr;
@@ -243,6 +245,7 @@ void build_plan(Plan& p, Arena& a) {
     const int N = p.N;
     for (int n = 0; n < N; ++n) {
         p.U32[n] = a.take<float>(p.s[n] * p.R[n]);
+        if (p.kind[n] == SMALL) p.Vsm[n] = a.take<double>(p.s[n] * p.s[n]);
         p.U64[n] = a.take<double>(p.s[n] * p.R[n]);
     }
     const int64_t Xn = prod(p.s, 0, N);
@@ -617,7 +620,10 @@ void update_factor(Run& r, int n, bool cold) {
     Plan& p = r.p;
     if (p.kind[n] == FIXED) return;
     if (p.kind[n] == SMALL) {
-        TK_HIP(jacobi_eig(p.S64, (int)p.s[n], (int)p.R[n], p.U64[n], p.U32[n], nullptr, r.st));
+        // warm start from the basis of the previous update once the cold start has run in this call
+        TK_HIP(jacobi_eig(p.S64, (int)p.s[n], (int)p.R[n], p.U64[n], p.U32[n], nullptr, r.st, p.Vsm[n],
+                          !cold && p.vsm_valid[n]));
+        if (cold) p.vsm_valid[n] = true;
         return;
     }
     if (cold) {

@@ -143,8 +143,9 @@ int64_t chol_counter_ints(int64_t n);
 
 // Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading
 // r eigenvectors (descending) to U64 (n x r fp64) and U32 (n x r fp32, nullable), all
-// eigenvalues descending to lam (nullable).
+// eigenvalues descending to lam (nullable).  Vio (nullable, n x n): receives the whole sorted
+// eigenvector basis; with warm, it also supplies the starting basis (a previous result).
 hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam,
-                      hipStream_t s);
+                      hipStream_t s, double* Vio = nullptr, bool warm = false);
 
 }  // namespace tk

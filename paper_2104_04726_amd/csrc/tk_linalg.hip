@@ -566,9 +566,10 @@ __global__ __launch_bounds__(256) void finish_factor_kernel(const int* need, con
 // ---------------------------------------------------------------- Jacobi
 __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ S, int n, int r,
                                                      double* __restrict__ U64, float* __restrict__ U32,
-                                                     double* __restrict__ lam) {
+                                                     double* __restrict__ lam, double* __restrict__ Vio,
+                                                     int warm) {
     constexpr int NM = 64, LD = 65;
-    __shared__ double A[NM * LD], V[NM * LD];
+    __shared__ double A[NM * LD], V[NM * LD], Tw[NM * LD];
     __shared__ double cs[NM / 2], sn[NM / 2];
     __shared__ int pp[NM / 2], qq[NM / 2];
     __shared__ double red[256];
@@ -579,9 +580,35 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
         double v = 0.0;
         if (i < n && j < n) v = 0.5 * (S[i * n + j] + S[j * n + i]);
         A[i * LD + j] = v;
-        V[i * LD + j] = (i == j) ? 1.0 : 0.0;
+        double w = (i == j) ? 1.0 : 0.0;
+        if (warm && i < n && j < n) w = Vio[i * n + j];
+        V[i * LD + j] = w;
     }
     __syncthreads();
+    if (warm) {
+        // start from the previous eigenvector basis V0: A <- V0^T S V0 (nearly diagonal when S has
+        // changed little), the rotations then accumulate onto V0
+        for (int e = tid; e < n2 * n2; e += blockDim.x) {
+            const int i = e / n2, j = e % n2;
+            double t = 0.0;
+            for (int k = 0; k < n2; ++k) t = fma(A[i * LD + k], V[k * LD + j], t);
+            Tw[i * LD + j] = t;
+        }
+        __syncthreads();
+        for (int e = tid; e < n2 * n2; e += blockDim.x) {
+            const int i = e / n2, j = e % n2;
+            if (j > i) continue;
+            double t = 0.0, u = 0.0;
+            for (int k = 0; k < n2; ++k) {
+                t = fma(V[k * LD + i], Tw[k * LD + j], t);
+                u = fma(V[k * LD + j], Tw[k * LD + i], u);
+            }
+            const double v = 0.5 * (t + u);
+            A[i * LD + j] = v;
+            A[j * LD + i] = v;
+        }
+        __syncthreads();
+    }
     const int npair = n2 / 2;
     for (int sweep = 0; sweep < 40 && n2 > 1; ++sweep) {
         double off = 0.0, tot = 0.0;
@@ -671,11 +698,12 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double* __restrict__ 
     for (int e = tid; e < n * n; e += blockDim.x) {
         const int row = e / n, i = e % n;
         const int k = rank[i];
+        const double v = V[row * LD + i];
         if (k < r) {
-            const double v = V[row * LD + i];
             U64[row * r + k] = v;
             if (U32) U32[row * r + k] = (float)v;
         }
+        if (Vio) Vio[row * n + k] = v;     // the whole sorted basis, for the next warm start
     }
 }
 
@@ -720,9 +748,11 @@ hipError_t finish_factor(const int* need, const double* Q1, double* U64, float* 
     return hipGetLastError();
 }
 
-hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam, hipStream_t s) {
+hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam, hipStream_t s,
+                      double* Vio, bool warm) {
     if (n < 1 || n > 64 || r < 1 || r > n) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, s, S, n, r, U64, U32, lam);
+    if (warm && !Vio) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, s, S, n, r, U64, U32, lam, Vio, warm ? 1 : 0);
     return hipGetLastError();
 }
 
