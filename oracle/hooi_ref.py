@@ -16,7 +16,7 @@ Paper passages followed (Sharma & Grover, arXiv 2104.04726):
   takes the R_n leading left singular vectors of Y(n)_(n), obtained as the leading
   eigenvectors of the Gram matrix Y(n)_(n) Y(n)_(n)^T (the text right after eq. (8)).
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
 
 * eq. (4) says the HOSVD factor is "the SVD of the unfolding of Q"; it is read as the left
   singular vectors of the unfolding of the *data* tensor, which is what eq. (6)-(7) use.

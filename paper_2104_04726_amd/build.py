@@ -19,10 +19,13 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtucker_mi355x.so")
 ARCH = "gfx950"
 
-# Packed FP32 instructions are disabled for every device compilation.
+# Packed FP32 instructions (v_pk_*_f32) are kept out of every device compilation.
+# MFMA accumulators are kept in VGPRs (gfx950 allows either register file): with the default
+# choice the compiler copied every accumulator between the two files once per k-tile.
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", CSRC, "-I", INCLUDE,
 ]
 
