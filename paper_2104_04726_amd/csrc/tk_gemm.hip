@@ -23,6 +23,10 @@
 #ifndef TK_F64_BK
 #define TK_F64_BK 16
 #endif
+// two LDS stages for the vector-load FP32 kernels as well (1) or only for the scalar-load ones (0)
+#ifndef TK_F32_DB_VEC
+#define TK_F32_DB_VEC 0
+#endif
 
 namespace tk {
 namespace {
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // FP32 tiles with scalar loads use two LDS stages (the next k-tile is stored into one while the
     // other is multiplied, one barrier per k-tile); measured slower for the vector-load and FP64
     // variants, which keep one stage (barrier, store, barrier)
-    constexpr bool DB = VEC == 0 && sizeof(T) == 4;
+    constexpr bool DB = (VEC == 0 || (VEC == 4 && TK_F32_DB_VEC)) && sizeof(T) == 4;
     constexpr int NST = DB ? 2 : 1;
     __shared__ __attribute__((aligned(16))) T As2[NST * ASZ];
     __shared__ __attribute__((aligned(16))) T Bs2[NST * BSZ];
