@@ -538,13 +538,24 @@ __global__ __launch_bounds__(256) void orth_check_kernel(const double* __restric
         last = (t == (int)gridDim.x - 1);
     }
     __syncthreads();
-    if (last && threadIdx.x == 0) {
-        double mx = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) {
-            const double o = __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (o > mx || o != o) mx = o;
+    if (!last) return;
+    // the last block: one block maximum per thread, then the same tree as above
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256) {
+        const double o = __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o > mx || o != o) mx = o;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
         }
-        const int nd = !(mx <= tol);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int nd = !(red[0] <= tol);
         *need = nd;
         if (nd && count) atomicAdd(count, 1);
         __hip_atomic_store(sync, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
