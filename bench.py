@@ -355,8 +355,11 @@ def main():
             entry.update(roofline_of(*work[name], per))
         stages[name] = entry
     roof = None
-    if any(n in work for n in stages):
-        dominant = max((n for n in stages if n in work), key=lambda n: stage_tot[n][0])
+    # the roofline object describes one kernel: the single-kernel stage with the largest total time
+    # (in FP32 the mode-update stages run two products and a split sum)
+    single = [n for n in stages if n in work and (args.precision != "fp32" or not n.startswith("gram"))]
+    if single:
+        dominant = max(single, key=lambda n: stage_tot[n][0])
         kind, amount = work[dominant]
         roof = roofline_of(kind, amount, stage_tot[dominant][0] / stage_tot[dominant][1])
         traffic = measured_traffic(dominant) if (args.precision == "fp32" and args.workload == "stack1080") else None
