@@ -638,7 +638,8 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
             const bool segok = d.seg >= (int64_t(1) << 61) || (d.seg % 2 == 0 && d.segstride % 2 == 0);
             return segok && d.ld % 2 == 0 && (((uintptr_t)d.ptr) & 7) == 0;
         };
-        if (ok2(g.a) && ok2(g.b) && g.a.seg == g.b.seg && g.a.segstride == g.b.segstride && g.k_split % 2 == 0) {
+        // one k position for both operands: equal segment lengths (each keeps its own stride)
+        if (ok2(g.a) && ok2(g.b) && g.a.seg == g.b.seg && g.k_split % 2 == 0) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 2>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
