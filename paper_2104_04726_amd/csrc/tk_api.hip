@@ -32,6 +32,7 @@
 using namespace tk;
 
 hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s);
+hipError_t tk_sum_splits_to_f32(const double* P, int nsplit, int64_t n, int64_t zstride, float* out, hipStream_t s);
 hipError_t tk_set_int(int* p, int v, hipStream_t s);
 hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_t s);
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
@@ -663,9 +664,23 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
         g.K = s;
         g.a = plain(p.U32[n], R);          // A(m = r, k = i) = U[i][r]
         g.b = folded(Y, B, B, s * B);      // B(k = i, n = (a, b)) = Y[a][i][b]
-        g.c = plain(W, AB);
-        g.c_f32 = 1;
-        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
+        // K split in two when the 64 x 64 tiles alone leave the CUs unevenly loaded (FP64 partials,
+        // summed in order and rounded once)
+        const int64_t cus = device_cu_count();
+        const int64_t tw = ((R + 63) / 64) * ((AB + 63) / 64);
+        auto balance = [&](int64_t t) { return ((double)t / cus) / (double)((t + cus - 1) / cus); };
+        const bool split_w = s >= 512 && 2 * R * AB <= p.Wpart_elems && balance(2 * tw) > 1.05 * balance(tw);
+        if (split_w) {
+            g.k_split = (((s + 1) / 2) + 15) / 16 * 16;
+            g.c = plain(p.Wpart, AB);
+            g.c_zstride = R * AB;
+            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
+            TK_HIP(tk_sum_splits_to_f32(p.Wpart, (int)((s + g.k_split - 1) / g.k_split), R * AB, R * AB, W, r.st));
+        } else {
+            g.c = plain(W, AB);
+            g.c_f32 = 1;
+            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
+        }
         // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W[r][(a,b)], K split to fill the chip
         GemmArgs h{};
         h.alpha = 1.0;
@@ -1170,8 +1185,9 @@ __global__ void fit_push_kernel(const double* __restrict__ src, int* counter, do
         *counter = k + 1;
     }
 }
+template <typename TO>
 __global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int64_t n, int64_t zstride,
-                                  double* __restrict__ out) {
+                                  TO* __restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         int z = 0;
@@ -1184,7 +1200,7 @@ __global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int6
             s += a3;
         }
         for (; z < nsplit; ++z) s += P[(int64_t)z * zstride + e];
-        out[e] = s;
+        out[e] = (TO)s;
     }
 }
 __global__ void resid_kernel(const float* __restrict__ X, const float* __restrict__ Xh, int64_t n,
@@ -1217,7 +1233,14 @@ hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_
 hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s) {
     int64_t g = (n + 255) / 256;
     g = std::max<int64_t>(1, std::min<int64_t>(g, 4096));
-    hipLaunchKernelGGL(sum_splits_kernel, dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
+    hipLaunchKernelGGL(sum_splits_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
+    return hipGetLastError();
+}
+// the same FP64 sum, rounded once to FP32
+hipError_t tk_sum_splits_to_f32(const double* P, int nsplit, int64_t n, int64_t zstride, float* out, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+    hipLaunchKernelGGL(sum_splits_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
     return hipGetLastError();
 }
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,

@@ -56,6 +56,8 @@ hipError_t gemm_f64(const GemmArgs& g, Orient oa, Orient ob, Epilogue epi, bool 
                     bool b_is_f32, hipStream_t s);
 // workgroups of the FP64 Gram kernel (FP32 operands, both k-contiguous) resident per CU (0 if unknown)
 int gram_f64_blocks_per_cu();
+// compute units of the current device (queried once per process; 256 when no device answers)
+int device_cu_count();
 // number of blocks gemm_* launches for these arguments (for EPI_RESID partial sizing)
 int64_t gemm_grid_blocks(const GemmArgs& g, bool f64);
 

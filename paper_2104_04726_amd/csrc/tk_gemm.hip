@@ -672,24 +672,12 @@ hipError_t by_orient(const GemmArgs& g, Orient oa, Orient ob, hipStream_t s) {
     return launch_one<T, TA, TB, MK, MK, EPI, ACC64, BM, BN, BK>(g, s);
 }
 
-int device_cus() {
-    static std::atomic<int> cached{0};
-    int c = cached.load(std::memory_order_relaxed);
-    if (c > 0) return c;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        c <= 0)
-        c = 256;
-    cached.store(c, std::memory_order_relaxed);
-    return c;
-}
-
 // 128 x 64 instead of 128 x 128 output tiles for an FP32 product when the wide tiles leave the CUs
 // unevenly loaded (average over maximum tiles per CU more than 5% better with narrow tiles) or
 // under-filled (fewer than 1.5 wide tiles per CU): measured 405 -> 376 us for 609 wide tiles and
 // 215 -> 203 us for 252, and slower where the wide tiles already balance.
 bool narrow_tiles_pay(const GemmArgs& g) {
-    const int64_t cus = device_cus();
+    const int64_t cus = device_cu_count();
     const int64_t tm = (g.M + 127) / 128;
     const int64_t t128 = tm * ((g.N + 127) / 128) * ((g.K + g.k_split - 1) / g.k_split);
     const int64_t t64 = tm * ((g.N + 63) / 64) * ((g.K + g.k_split - 1) / g.k_split);
@@ -733,6 +721,18 @@ hipError_t gemm_f64(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, boo
     if (a_is_f32) return by_orient<double, float, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
     if (b_is_f32) return by_orient<double, double, float, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
     return by_orient<double, double, double, EPI_STORE, false, 64, 64, 16>(g, oa, ob, s);
+}
+
+int device_cu_count() {
+    static std::atomic<int> cached{0};
+    int c = cached.load(std::memory_order_relaxed);
+    if (c > 0) return c;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+        c = 256;
+    cached.store(c, std::memory_order_relaxed);
+    return c;
 }
 
 int gram_f64_blocks_per_cu() {
