@@ -650,45 +650,57 @@ bool direct_update_ok(const Run& r, int n) {
     return p.tree && p.kind[n] == LARGE && r.inner_override <= 0 && r.ctx->opt.inner_iters == 1;
 }
 
-void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int n, int stage_prod, int stage_oi) {
+// The W product of a one-step update: W = Uw^T Yw with Uw (K x Rw, FP32 factor, m = r contiguous)
+// and Yw given as the k-major operand desc (k = contraction index, n = the other indices).  Stored
+// to Wout (Rw x N, FP32).
+struct WProduct {
+    const float* U;
+    int64_t R, K, N;
+    Desc y;
+};
+
+void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int n, const WProduct& wp, const Desc& wz,
+                   int stage_prod, int stage_oi) {
     Plan& p = r.p;
     const int64_t R = p.R[n], AB = A * B;
-    if (R * AB > 2 * p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "direct update buffer too small"};
+    if (wp.R * wp.N > 2 * p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "direct update buffer too small"};
     float* W = (float*)p.P;
     {
         StageTimer t(r, stage_prod);
         GemmArgs g{};
         g.alpha = 1.0;
-        g.M = R;
-        g.N = AB;
-        g.K = s;
-        g.a = plain(p.U32[n], R);          // A(m = r, k = i) = U[i][r]
-        g.b = folded(Y, B, B, s * B);      // B(k = i, n = (a, b)) = Y[a][i][b]
+        g.M = wp.R;
+        g.N = wp.N;
+        g.K = wp.K;
+        g.a = plain(wp.U, wp.R);           // A(m = r, k = i) = U[i][r]
+        g.b = wp.y;
         // K split in two when the 64 x 64 tiles alone leave the CUs unevenly loaded (FP64 partials,
         // summed in order and rounded once)
         const int64_t cus = device_cu_count();
-        const int64_t tw = ((R + 63) / 64) * ((AB + 63) / 64);
+        const int64_t tw = ((wp.R + 63) / 64) * ((wp.N + 63) / 64);
         auto balance = [&](int64_t t) { return ((double)t / cus) / (double)((t + cus - 1) / cus); };
-        const bool split_w = s >= 512 && 2 * R * AB <= p.Wpart_elems && balance(2 * tw) > 1.05 * balance(tw);
+        const bool split_w =
+            wp.K >= 512 && 2 * wp.R * wp.N <= p.Wpart_elems && balance(2 * tw) > 1.05 * balance(tw);
         if (split_w) {
-            g.k_split = (((s + 1) / 2) + 15) / 16 * 16;
-            g.c = plain(p.Wpart, AB);
-            g.c_zstride = R * AB;
+            g.k_split = (((wp.K + 1) / 2) + 15) / 16 * 16;
+            g.c = plain(p.Wpart, wp.N);
+            g.c_zstride = wp.R * wp.N;
             TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
-            TK_HIP(tk_sum_splits_to_f32(p.Wpart, (int)((s + g.k_split - 1) / g.k_split), R * AB, R * AB, W, r.st));
+            TK_HIP(tk_sum_splits_to_f32(p.Wpart, (int)((wp.K + g.k_split - 1) / g.k_split), wp.R * wp.N, wp.R * wp.N,
+                                        W, r.st));
         } else {
-            g.c = plain(W, AB);
+            g.c = plain(W, wp.N);
             g.c_f32 = 1;
             TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
         }
-        // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W[r][(a,b)], K split to fill the chip
+        // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W(k = (a, b), r), K split to fill the chip
         GemmArgs h{};
         h.alpha = 1.0;
         h.M = s;
         h.N = R;
         h.K = AB;
         h.a = folded(Y, B, B, s * B);      // A(m = i, k = (a, b))
-        h.b = folded(W, AB, B, B);         // B(k = (a, b), n = r) = W[r][a][b], same k segments as A
+        h.b = wz;                          // B(k = (a, b), n = r), same k segments as A
         const int64_t tiles = ((s + 63) / 64) * ((R + 63) / 64);
         int64_t splits = std::max<int64_t>(1, std::min<int64_t>(gram_capacity() / tiles, AB / 256));
         splits = std::min<int64_t>(splits, std::max<int64_t>(1, p.Wpart_elems / (s * R)));
@@ -708,6 +720,14 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
     }
     StageTimer t(r, stage_oi);
     orthonormalize(r, p.Z, false, s, R, p.U64[n], p.U32[n], false);
+}
+
+// the plain form: W = Y x_n U_n^T from the same Y (viewed (A, s, B)), stored (R, A, B)
+void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int n, int stage_prod, int stage_oi) {
+    Plan& p = r.p;
+    const int64_t R = p.R[n], AB = A * B;
+    const WProduct wp{p.U32[n], R, s, AB, folded(Y, B, B, s * B)};
+    direct_update(r, Y, A, s, B, n, wp, folded(p.P, AB, B, B), stage_prod, stage_oi);
 }
 
 void identity_factor(Run& r, int n) {
@@ -806,7 +826,13 @@ void sweep_tree(Run& r) {
             StageTimer t(r, TUCKER_STAGE_TTM_Y2);
             ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
         }
-        if (direct_update_ok(r, 1)) {
+        if (direct_update_ok(r, 1) && p.kind[0] != FIXED) {
+            // Y1^T U2 = T34 x_1 U1^T x_2 U2^T = Y0 x_1 U1^T: contracted over s1 from Y0 (still resident
+            // from mode 1, computed with the same U2) instead of over s2 from Y1; W(r1, r2, c)
+            const WProduct wp{p.U32[0], R0, s0, R1 * R23, plain(p.Y0, R1 * R23)};
+            direct_update(r, p.Y1, R0, s1, R23, 1, wp, folded(p.P, R23, R23, R1 * R23), TUCKER_STAGE_GRAM_2,
+                          TUCKER_STAGE_OI_2);
+        } else if (direct_update_ok(r, 1)) {
             direct_update(r, p.Y1, R0, s1, R23, 1, TUCKER_STAGE_GRAM_2, TUCKER_STAGE_OI_2);
         } else {
             int64_t dy[3] = {R0, s1, R23};
