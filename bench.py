@@ -62,7 +62,8 @@ def stage_work(dims, ranks, precision="fp32"):
             "pass_a": ("hbm", 4 * (s0 * s1 * L + s0 * s1 * r23)),
             "ttm_y1": ("f32", 2 * r1 * s1 * (s0 * r23)),
             "gram_1": ("f64", 4 * s0 * r0 * (r1 * r23)),
-            "ttm_y2": ("f32", 2 * r0 * s0 * (s1 * r23)),
+            # Y2 = T1 x_3 U3^T x_4 U4^T: the fibre kernel on T1 (pass C1 runs before mode 2)
+            "ttm_y2": ("hbm", 4 * (r0 * s1 * L + r0 * s1 * r23)),
             # mode 2: W = Y1 x_1 U1^T from the mode-1 tensor (contracted over s1), then Y2_(2) W_(2)^T
             "gram_2": ("f64", 2 * r0 * s0 * (r1 * r23) + 2 * s1 * r1 * (r0 * r23)),
             "pass_c1": ("f32", 2 * r0 * s0 * (s1 * L)),

@@ -819,12 +819,19 @@ void sweep_tree(Run& r) {
             update_factor(r, 0, false);
         }
     }
-    // mode 2: Y1 = T34 x_1 U1^T (new U1), S1
+    // second full-tensor pass T1 = X x_1 U1^T: it needs only the new U1, so it runs before mode 2
+    int64_t dc[3] = {s0, s1, L};
+    {
+        StageTimer t(r, TUCKER_STAGE_PASS_C1);
+        ttm(r, r.X, dc, 3, 0, p.U32[0], R0, false, p.T1);
+    }
+    // mode 2: Y1 = T34 x_1 U1^T = T1 x_3 U3^T x_4 U4^T (distinct modes commute), formed from T1 by
+    // the memory-bound fibre kernel instead of a product over s1
     if (p.kind[1] != FIXED) {
-        int64_t d[3] = {s0, s1, R23};
         {
             StageTimer t(r, TUCKER_STAGE_TTM_Y2);
-            ttm(r, p.T34, d, 3, 0, p.U32[0], R0, false, p.Y1);
+            TK_HIP(pair_ttm(p.T1, R0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.Y1,
+                            r.st));
         }
         if (direct_update_ok(r, 1) && p.kind[0] != FIXED) {
             // Y1^T U2 = T34 x_1 U1^T x_2 U2^T = Y0 x_1 U1^T: contracted over s1 from Y0 (still resident
@@ -841,16 +848,11 @@ void sweep_tree(Run& r) {
             update_factor(r, 1, false);
         }
     }
-    // T12 = X x_1 U1^T x_2 U2^T (second full-tensor pass)
+    // T12 = T1 x_2 U2^T
     {
-        int64_t d[3] = {s0, s1, L};
-        {
-            StageTimer t(r, TUCKER_STAGE_PASS_C1);
-            ttm(r, r.X, d, 3, 0, p.U32[0], R0, false, p.T1);
-        }
-        d[0] = R0;
+        dc[0] = R0;
         StageTimer t(r, TUCKER_STAGE_TTM_C2);
-        ttm(r, p.T1, d, 3, 1, p.U32[1], R1, false, p.T12);
+        ttm(r, p.T1, dc, 3, 1, p.U32[1], R1, false, p.T12);
     }
     // modes 3 and 4 from the fibre Gram of T12
     if (p.kind[2] != FIXED || p.kind[3] != FIXED) {
