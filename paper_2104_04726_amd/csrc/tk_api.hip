@@ -477,16 +477,20 @@ void gram(Run& r, const float* in, const int64_t* dims, int N, int n, int stage 
 }
 
 // W = A^T A (FP64) for A (rows x cols), A float or double, split over rows
-void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, double* W) {
+// W = A^T A (cols x cols, FP64); lower: only the tiles on and below the diagonal are formed (the
+// Cholesky and the orthogonality check read only the lower triangle)
+void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, double* W, bool lower = false) {
     Plan& p = r.p;
     GemmArgs g{};
     g.alpha = 1.0;
     g.M = cols;
     g.N = cols;
+    g.lower_only = lower ? 1 : 0;
     g.K = rows;
     g.a = plain(A, cols);
     g.b = plain(A, cols);
-    const int64_t tiles = ((cols + 63) / 64) * ((cols + 63) / 64);
+    const int64_t t = (cols + 63) / 64;
+    const int64_t tiles = lower ? t * (t + 1) / 2 : t * t;
     int64_t splits = std::max<int64_t>(1, std::min<int64_t>(16, (512 + tiles - 1) / tiles));
     splits = std::min<int64_t>(splits, std::max<int64_t>(1, rows / 64));
     int64_t ks = (rows + splits - 1) / splits;
@@ -523,9 +527,10 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
     g.N = cols;
     g.K = cols;
     g.a = plain(A, cols);      // (m=row, k) at row*cols + k
-    g.b = plain(Tm, cols);     // (k, n) = T[n][k] -> NK
+    g.b = plain(Tm, cols);     // (k, n) = T[n][k] -> NK; T lower triangular: zero for k > n
     g.c = plain(Q, cols);
     g.k_split = 0;
+    g.k_upto_n = 1;
     TK_HIP(gemm_f64(g, MK, MK, EPI_STORE, a32, false, r.st));
 }
 
@@ -548,7 +553,7 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     if (!cold && !U32) {
         // an intermediate step of the cold start: one CholeskyQR pass gives a basis of span(Z),
         // all that the next product S U needs; the last step delivers the orthonormal factor
-        gram_tn64(r, Z, z32, rows, cols, p.W);
+        gram_tn64(r, Z, z32, rows, cols, p.W, true);
         TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
         apply_tri(r, Z, z32, rows, cols, p.Tm, U64);
         return;
@@ -556,10 +561,10 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     const double u = std::ldexp(1.0, -53);
     const double shift = cold ? 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols : 0.0;
     // pass 1: Z -> Q1
-    gram_tn64(r, Z, z32, rows, cols, p.W);
+    gram_tn64(r, Z, z32, rows, cols, p.W, true);
     TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
     apply_tri(r, Z, z32, rows, cols, p.Tm, p.Q1);
-    gram_tn64(r, p.Q1, false, rows, cols, p.W);
+    gram_tn64(r, p.Q1, false, rows, cols, p.W, true);
     if (!cold) {
         // pass 2 only where needed: need = p.shifts[2], counted in p.shifts[1]
         int* need = p.shifts + 2;
@@ -571,7 +576,7 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     } else {
         TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
-        gram_tn64(r, U64, false, rows, cols, p.W);
+        gram_tn64(r, U64, false, rows, cols, p.W, true);
         TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
         apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
         TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));

@@ -46,6 +46,7 @@ struct GemmArgs {
     double* resid_partial;   // EPI_RESID: one double per block
     const int* run_if;       // nullable: the launch does nothing when *run_if == 0
     int c_f32;               // FP64 kernels, EPI_STORE: write c as float (rounded once)
+    int k_upto_n;            // B(k, n) = 0 for k > n: a tile's k range ends at its last column
 };
 
 // fp32 MFMA GEMM (operands fp32, accumulation fp32; acc64 = FP64 accumulation across k-tiles)
@@ -133,7 +134,8 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // run_if (nullable): every kernel of the call returns at once when *run_if == 0.
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
                            double* dsc, int* shifts, hipStream_t s, const int* run_if = nullptr);
-// need[0] = 1 (and ++count[0]) when max_ij |W_ij - delta_ij| > tol, else 0 (n x n FP64), in one
+// need[0] = 1 (and ++count[0]) when max_{i>=j} |W_ij - delta_ij| > tol, else 0 (n x n FP64, symmetric:
+// only the lower triangle is read), in one
 // launch.  partial: orth_check_partials() doubles of scratch; sync: an int that is zero on entry
 // (and zero again afterwards).
 hipError_t orth_check(const double* W, int64_t n, double tol, double* partial, int* need, int* count, int* sync,

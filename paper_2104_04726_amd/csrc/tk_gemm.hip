@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (tn >= tilesN || tm >= tilesM) return;
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int64_t kbeg = (int64_t)blockIdx.z * g.k_split;
-    const int64_t kend = (kbeg + g.k_split < g.K) ? kbeg + g.k_split : g.K;
+    int64_t kend = (kbeg + g.k_split < g.K) ? kbeg + g.k_split : g.K;
+    if (g.k_upto_n && n0 + BN < kend) kend = n0 + BN;   // triangular B: the rest of k contributes zero
 
     const TA* __restrict__ pa = (const TA*)g.a.ptr;
     const TB* __restrict__ pb = (const TB*)g.b.ptr;

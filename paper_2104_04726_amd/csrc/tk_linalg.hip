@@ -520,7 +520,9 @@ __global__ __launch_bounds__(256) void orth_check_kernel(const double* __restric
     double m = 0.0;
     const int64_t total = n * n;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const double a = fabs(W[e] - ((e / n == e % n) ? 1.0 : 0.0));
+        const int64_t row = e / n, col = e - row * n;
+        if (col > row) continue;            // the lower triangle (W symmetric; only it is formed)
+        const double a = fabs(W[e] - ((row == col) ? 1.0 : 0.0));
         m = (a > m || a != a) ? a : m;
     }
     red[threadIdx.x] = m;
