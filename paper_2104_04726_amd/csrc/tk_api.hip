@@ -590,9 +590,22 @@ void orth_iter(Run& r, int n, int q, bool cold) {
     const int64_t s = p.s[n], R = p.R[n];
     // Z = S U has few output tiles ((s/64) x (R/64)); K is split so that the grid fills the chip,
     // the FP64 partials summed in a fixed order
+    // split count: the best per-CU balance of workgroups (average over maximum per CU), counting
+    // fewer than two per CU as under-filled; ties go to fewer splits (less partial-sum traffic)
     const int64_t tiles = ((s + 63) / 64) * ((R + 63) / 64);
-    int64_t splits = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, s / 128));
-    splits = std::min<int64_t>(splits, p.Wpart_elems / std::max<int64_t>(1, s * R));
+    const int64_t cus = device_cu_count();
+    const int64_t maxsp = std::max<int64_t>(1, std::min<int64_t>(
+                                                   std::min<int64_t>(16, s / 128), p.Wpart_elems / std::max<int64_t>(1, s * R)));
+    int64_t splits = 1;
+    double best = -1.0;
+    for (int64_t sp = 1; sp <= maxsp; ++sp) {
+        const int64_t b = tiles * sp;
+        const double score = ((double)b / cus) / (double)((b + cus - 1) / cus) * std::min(1.0, (double)b / (2.0 * cus));
+        if (score > best + 1e-9) {
+            best = score;
+            splits = sp;
+        }
+    }
     int64_t ks = (s + splits - 1) / splits;
     ks = (ks + 15) / 16 * 16;
     const int nsplit = (int)((s + ks - 1) / ks);
