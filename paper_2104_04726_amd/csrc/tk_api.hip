@@ -50,6 +50,8 @@ struct tucker_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pool;   // stage timer events (created on first use)
     bool async_alloc = false;       // workspace from the stream-ordered allocator (server slots)
+    hipStream_t aux = nullptr;      // second stream: the cold start of mode 1 beside that of mode 2
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -131,6 +133,15 @@ struct Plan {
     void* chol_ws = nullptr;     // task-graph counters of the Cholesky (zero between calls)
     double* chol_dsc = nullptr;
     int64_t chol_cap = 0;        // largest order the counters are sized for
+    // second orthogonal-iteration scratch set (Gram, products, CholeskyQR, counters), so that the
+    // cold starts of the two large modes of a tree shape can run on two streams; swap_oi exchanges
+    // it with the first
+    bool has_alt = false;
+    double *S64b = nullptr, *Wpartb = nullptr, *Zb = nullptr, *Q1b = nullptr, *Wb = nullptr, *Tmb = nullptr;
+    double *chol_dscb = nullptr, *redb = nullptr;
+    void* chol_wsb = nullptr;
+    int* shiftsb = nullptr;
+    int64_t Wpartb_elems = 0, chol_capb = 0;
     double* F = nullptr;
     double* Fpart = nullptr;
     // norms and fits
@@ -324,6 +335,37 @@ void build_plan(Plan& p, Arena& a) {
     p.fits = a.take<double>(p.max_iters + p.refine + 2);
     p.shifts = a.take<int>(8);
     if (!p.tree) p.Xh = (p.kind[0] == LARGE && p.s[0] > kSmallMode) ? nullptr : a.take<float>(Xn);
+    p.has_alt = p.tree && p.kind[0] == LARGE && p.kind[1] == LARGE;
+    if (p.has_alt) {
+        const int64_t s0 = p.s[0], R0 = p.R[0];
+        p.S64b = a.take<double>(s0 * s0);
+        p.Zb = a.take<double>(s0 * R0);
+        p.Q1b = a.take<double>(s0 * R0);
+        p.Wb = a.take<double>(R0 * R0);
+        p.Wpartb_elems = std::max<int64_t>(16 * R0 * R0, 8 * s0 * R0);
+        p.Wpartb = a.take<double>(p.Wpartb_elems);
+        p.Tmb = a.take<double>(R0 * R0);
+        p.chol_wsb = a.take<int>(chol_counter_ints(R0));
+        p.chol_dscb = a.take<double>(R0);
+        p.chol_capb = R0;
+        p.redb = a.take<double>(kSumsqBlocks);
+        p.shiftsb = a.take<int>(8);
+    }
+}
+
+void swap_oi(Plan& p) {
+    std::swap(p.S64, p.S64b);
+    std::swap(p.Wpart, p.Wpartb);
+    std::swap(p.Wpart_elems, p.Wpartb_elems);
+    std::swap(p.Z, p.Zb);
+    std::swap(p.Q1, p.Q1b);
+    std::swap(p.W, p.Wb);
+    std::swap(p.Tm, p.Tmb);
+    std::swap(p.chol_ws, p.chol_wsb);
+    std::swap(p.chol_dsc, p.chol_dscb);
+    std::swap(p.chol_cap, p.chol_capb);
+    std::swap(p.red, p.redb);
+    std::swap(p.shifts, p.shiftsb);
 }
 
 // ------------------------------------------------------------------ driver state
@@ -516,7 +558,28 @@ void gram_tn64(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, doub
 void reset_counters(Run& r) {
     TK_HIP(fill_zero(r.p.shifts, 8 * (int64_t)sizeof(int), r.st));
     if (r.p.chol_ws) TK_HIP(fill_zero(r.p.chol_ws, chol_counter_ints(r.p.chol_cap) * (int64_t)sizeof(int), r.st));
+    if (r.p.has_alt) {
+        TK_HIP(fill_zero(r.p.shiftsb, 8 * (int64_t)sizeof(int), r.st));
+        TK_HIP(fill_zero(r.p.chol_wsb, chol_counter_ints(r.p.chol_capb) * (int64_t)sizeof(int), r.st));
+    }
 }
+
+// work enqueued after fork_aux on ctx->aux (under OnAux) runs after everything queued on the main
+// stream so far; join_aux makes the main stream wait for it
+void fork_aux(Run& r) {
+    TK_HIP(hipEventRecord(r.ctx->fork_ev, r.st));
+    TK_HIP(hipStreamWaitEvent(r.ctx->aux, r.ctx->fork_ev, 0));
+}
+void join_aux(Run& r) {
+    TK_HIP(hipEventRecord(r.ctx->join_ev, r.ctx->aux));
+    TK_HIP(hipStreamWaitEvent(r.st, r.ctx->join_ev, 0));
+}
+struct OnAux {
+    Run& r;
+    hipStream_t main;
+    explicit OnAux(Run& run) : r(run), main(run.st) { r.st = r.ctx->aux; }
+    ~OnAux() { r.st = main; }
+};
 
 void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, const double* Tm, double* Q,
                const int* run_if = nullptr) {
@@ -789,10 +852,30 @@ void core_norm_and_fit(Run& r, double* fit_slot) {
 // ------------------------------------------------------------------ T-HOSVD initialisation
 void thosvd(Run& r) {
     Plan& p = r.p;
+    int n0 = 0;
+    if (p.has_alt) {
+        // the two large modes start from the unprojected X independently: both Grams on the main
+        // stream (mode 1's into the second scratch set), then the latency-bound cold orthogonal
+        // iterations of mode 1 on the second stream beside those of mode 2
+        swap_oi(p);
+        gram(r, r.X, p.s, p.N, 0);
+        swap_oi(p);
+        gram(r, r.X, p.s, p.N, 1);
+        fork_aux(r);
+        swap_oi(p);
+        {
+            OnAux aux(r);
+            update_factor(r, 0, true);
+        }
+        swap_oi(p);
+        update_factor(r, 1, true);
+        join_aux(r);
+        n0 = 2;
+    }
     // tree shapes: the Grams of the two small trailing modes come from the fibre Gram of X (one
     // coalesced pass over X), F = sum_(h,w) x_(h,w) x_(h,w)^T over the (s3 s4)-long fibres
     bool have_f = false;
-    for (int n = 0; n < p.N; ++n) {
+    for (int n = n0; n < p.N; ++n) {
         if (p.kind[n] == FIXED) {
             identity_factor(r, n);
             continue;
@@ -1411,6 +1494,12 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
             return TUCKER_ERR_DEVICE;
         }
     }
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        tucker_destroy(c);
+        return TUCKER_ERR_DEVICE;
+    }
     *out = c;
     return TUCKER_OK;
 }
@@ -1424,6 +1513,12 @@ tucker_status tucker_destroy(tucker_ctx* ctx) {
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return TUCKER_OK;
@@ -1571,8 +1666,9 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         double fexact = 0.0;
         TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (total + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         TK_HIP(hipMemcpyAsync(&fexact, p.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-        int shifts2[4] = {0, 0, 0, 0};
+        int shifts2[4] = {0, 0, 0, 0}, shifts3[4] = {0, 0, 0, 0};
         TK_HIP(hipMemcpyAsync(shifts2, p.shifts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (p.has_alt) TK_HIP(hipMemcpyAsync(shifts3, p.shiftsb, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
         *fit = fexact;
         if (fit_history)
@@ -1592,8 +1688,8 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         ctx->stats.fit_gram = fits[total];
         ctx->stats.sweeps = done;
         ctx->stats.refine_sweeps = p.refine;
-        ctx->stats.chol_shifts = shifts2[0];
-        ctx->stats.orth_second_passes = shifts2[1];
+        ctx->stats.chol_shifts = shifts2[0] + shifts3[0];
+        ctx->stats.orth_second_passes = shifts2[1] + shifts3[1];
         ctx->stats.workspace_bytes = ctx->ws_bytes;
         if (!std::isfinite(fexact)) throw Fail{TUCKER_ERR_NUMERICAL, "non-finite fit"};
     });
