@@ -852,45 +852,51 @@ void core_norm_and_fit(Run& r, double* fit_slot) {
 // ------------------------------------------------------------------ T-HOSVD initialisation
 void thosvd(Run& r) {
     Plan& p = r.p;
-    int n0 = 0;
-    if (p.has_alt) {
-        // the two large modes start from the unprojected X independently: both Grams on the main
-        // stream (mode 1's into the second scratch set), then the latency-bound cold orthogonal
-        // iterations of mode 1 on the second stream beside those of mode 2
-        swap_oi(p);
-        gram(r, r.X, p.s, p.N, 0);
-        swap_oi(p);
-        gram(r, r.X, p.s, p.N, 1);
-        fork_aux(r);
-        swap_oi(p);
-        {
-            OnAux aux(r);
-            update_factor(r, 0, true);
-        }
-        swap_oi(p);
-        update_factor(r, 1, true);
-        join_aux(r);
-        n0 = 2;
-    }
-    // tree shapes: the Grams of the two small trailing modes come from the fibre Gram of X (one
-    // coalesced pass over X), F = sum_(h,w) x_(h,w) x_(h,w)^T over the (s3 s4)-long fibres
-    bool have_f = false;
-    for (int n = n0; n < p.N; ++n) {
-        if (p.kind[n] == FIXED) {
-            identity_factor(r, n);
-            continue;
-        }
-        if (p.tree && n >= 2) {
-            if (!have_f) {
-                TK_HIP(fibre_gram(r.X, p.s[0] * p.s[1], (int)(p.s[2] * p.s[3]), p.Fpart, kFibreGramBlocks, p.F, r.st));
-                have_f = true;
+    // modes from `from` on, in order.  Tree shapes: the Grams of the two small trailing modes come
+    // from the fibre Gram of X (one coalesced pass over X), F = sum_(h,w) x_(h,w) x_(h,w)^T over
+    // the (s3 s4)-long fibres
+    auto modes_from = [&](int from) {
+        bool have_f = false;
+        for (int n = from; n < p.N; ++n) {
+            if (p.kind[n] == FIXED) {
+                identity_factor(r, n);
+                continue;
             }
-            TK_HIP(pair_mode_gram(p.F, (int)p.s[2], (int)p.s[3], nullptr, 0, n == 2 ? 3 : 4, p.S64, r.st));
-        } else {
-            gram(r, r.X, p.s, p.N, n);
+            if (p.tree && n >= 2) {
+                if (!have_f) {
+                    TK_HIP(fibre_gram(r.X, p.s[0] * p.s[1], (int)(p.s[2] * p.s[3]), p.Fpart, kFibreGramBlocks, p.F,
+                                      r.st));
+                    have_f = true;
+                }
+                TK_HIP(pair_mode_gram(p.F, (int)p.s[2], (int)p.s[3], nullptr, 0, n == 2 ? 3 : 4, p.S64, r.st));
+            } else {
+                gram(r, r.X, p.s, p.N, n);
+            }
+            update_factor(r, n, true);
         }
-        update_factor(r, n, true);
+    };
+    if (!p.has_alt) {
+        modes_from(0);
+        return;
     }
+    // the modes start from the unprojected X independently: both large-mode Grams on the main
+    // stream (mode 1's into the second scratch set); then the latency-bound cold orthogonal
+    // iterations of mode 1, followed by the small modes, on the second stream with that set, beside
+    // those of mode 2 on the main stream
+    swap_oi(p);
+    gram(r, r.X, p.s, p.N, 0);
+    swap_oi(p);
+    gram(r, r.X, p.s, p.N, 1);
+    fork_aux(r);
+    swap_oi(p);
+    {
+        OnAux aux(r);
+        update_factor(r, 0, true);
+        modes_from(2);
+    }
+    swap_oi(p);
+    update_factor(r, 1, true);
+    join_aux(r);
 }
 
 // ------------------------------------------------------------------ one ALS sweep
