@@ -142,6 +142,9 @@ struct Plan {
     void* chol_wsb = nullptr;
     int* shiftsb = nullptr;
     int64_t Wpartb_elems = 0, chol_capb = 0;
+    // capacities (elements) of S64 and Z in the active set and the other one, checked before a
+    // Gram or an orthogonal iteration writes them (0: not tracked)
+    int64_t S64_elems = 0, S64b_elems = 0, Z_elems = 0, Zb_elems = 0;
     double* F = nullptr;
     double* Fpart = nullptr;
     // norms and fits
@@ -311,11 +314,13 @@ void build_plan(Plan& p, Arena& a) {
         }
     }
     if (p.tree) pmax = std::max(pmax, prod(p.R, 0, N));   // W of the direct warm update (R_n x A x B)
-    p.S64 = a.take<double>(std::max<int64_t>(std::max(maxs, maxsmall) * std::max(maxs, maxsmall), 64 * 64));
+    p.S64_elems = std::max<int64_t>(std::max(maxs, maxsmall) * std::max(maxs, maxsmall), 64 * 64);
+    p.S64 = a.take<double>(p.S64_elems);
     p.P = a.take<double>(pmax);
     p.P_elems = pmax;
     const int64_t sR = max_large_sR(p), Rm = max_large_R(p);
     p.Z = a.take<double>(sR);
+    p.Z_elems = sR;
     p.Q1 = a.take<double>(sR);
     p.W = a.take<double>(Rm * Rm);
     p.Wpart_elems = std::max<int64_t>(16 * Rm * Rm, 8 * sR);
@@ -339,7 +344,9 @@ void build_plan(Plan& p, Arena& a) {
     if (p.has_alt) {
         const int64_t s0 = p.s[0], R0 = p.R[0];
         p.S64b = a.take<double>(s0 * s0);
+        p.S64b_elems = s0 * s0;
         p.Zb = a.take<double>(s0 * R0);
+        p.Zb_elems = s0 * R0;
         p.Q1b = a.take<double>(s0 * R0);
         p.Wb = a.take<double>(R0 * R0);
         p.Wpartb_elems = std::max<int64_t>(16 * R0 * R0, 8 * s0 * R0);
@@ -355,6 +362,8 @@ void build_plan(Plan& p, Arena& a) {
 
 void swap_oi(Plan& p) {
     std::swap(p.S64, p.S64b);
+    std::swap(p.S64_elems, p.S64b_elems);
+    std::swap(p.Z_elems, p.Zb_elems);
     std::swap(p.Wpart, p.Wpartb);
     std::swap(p.Wpart_elems, p.Wpartb_elems);
     std::swap(p.Z, p.Zb);
@@ -478,6 +487,7 @@ void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float
 void gram(Run& r, const float* in, const int64_t* dims, int N, int n, int stage = -1) {
     Plan& p = r.p;
     const int64_t A = prod(dims, 0, n), s = dims[n], B = prod(dims, n + 1, N);
+    if (p.S64_elems > 0 && s * s > p.S64_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram output buffer too small"};
     if (s <= kSmallMode) {
         StageTimer t(r, stage);
         TK_HIP(small_gram(in, A, s, B, p.Fpart, kFibreGramBlocks / 8, p.S64, r.st));
@@ -651,6 +661,8 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
 void orth_iter(Run& r, int n, int q, bool cold) {
     Plan& p = r.p;
     const int64_t s = p.s[n], R = p.R[n];
+    if ((p.S64_elems > 0 && s * s > p.S64_elems) || (p.Z_elems > 0 && s * R > p.Z_elems) || R > p.chol_cap)
+        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "orthogonal-iteration scratch set too small for this mode"};
     // Z = S U has few output tiles ((s/64) x (R/64)); K is split so that the grid fills the chip,
     // the FP64 partials summed in a fixed order
     // split count: the best per-CU balance of workgroups (average over maximum per CU), counting
@@ -879,23 +891,22 @@ void thosvd(Run& r) {
         modes_from(0);
         return;
     }
-    // the modes start from the unprojected X independently: both large-mode Grams on the main
-    // stream (mode 1's into the second scratch set); then the latency-bound cold orthogonal
-    // iterations of mode 1, followed by the small modes, on the second stream with that set, beside
-    // those of mode 2 on the main stream
-    swap_oi(p);
-    gram(r, r.X, p.s, p.N, 0);
-    swap_oi(p);
+    // the modes start from the unprojected X independently.  Mode 2's Gram (the larger) comes first,
+    // in the first scratch set (sized for the largest mode); its latency-bound cold orthogonal
+    // iterations then run on the second stream with that set, while the main stream, with the
+    // second set (sized for mode 1), forms mode 1's Gram (its split partials sit in a buffer the
+    // iterations do not use) and runs mode 1's iterations and the small modes
     gram(r, r.X, p.s, p.N, 1);
     fork_aux(r);
-    swap_oi(p);
     {
         OnAux aux(r);
-        update_factor(r, 0, true);
-        modes_from(2);
+        update_factor(r, 1, true);
     }
     swap_oi(p);
-    update_factor(r, 1, true);
+    gram(r, r.X, p.s, p.N, 0);
+    update_factor(r, 0, true);
+    modes_from(2);
+    swap_oi(p);
     join_aux(r);
 }
 
@@ -1758,6 +1769,7 @@ tucker_status tucker_gram(tucker_ctx* ctx, const float* in, int ndim, const int6
         with_scratch(ctx, [&](Arena& a) {
             p.Fpart = a.take<double>(64 * 64 * 64);
             p.S64 = a.take<double>(sdim * sdim);
+            p.S64_elems = sdim * sdim;
             p.P_elems = (int64_t)gram_splits(sdim, K) * sdim * sdim;
             p.P = a.take<double>(sdim > kSmallMode ? p.P_elems : 1);
         });
