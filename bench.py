@@ -302,8 +302,8 @@ def main():
         serve(args)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the decomposition is not "
-              "sharded across GPUs in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the decomposition runs on a "
+              "single GPU and is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -45,7 +45,7 @@ typedef enum {
     TUCKER_ERR_OUT_OF_MEMORY = 2, /* device allocation failed or exceeds hbm_budget_bytes */
     TUCKER_ERR_DEVICE = 3,        /* no usable GPU, or a HIP runtime error                */
     TUCKER_ERR_NUMERICAL = 4,     /* non-finite input norm, or an unrecoverable breakdown */
-    TUCKER_ERR_UNSUPPORTED = 5,   /* a valid request this build does not implement        */
+    TUCKER_ERR_UNSUPPORTED = 5,   /* a valid request the library does not implement       */
     TUCKER_ERR_TIMEOUT = 6        /* tucker_server_wait: the request has not finished yet */
 } tucker_status;
 
