@@ -11,8 +11,11 @@ Also reported (one JSON line on stdout):
                 steps, against the MI355X peak (HBM 8 TB/s, FP32 MFMA 157.3 TFLOP/s,
                 FP64 MFMA 78.6 TFLOP/s);
   stages        every timed stage (ms per launch, achieved rate);
-  cpu_baseline  the FP64 CPU oracle on the same tensor: T-HOSVD plus a sample of sweeps, timed on
-                the host cores and scaled to the same 20-sweep job.
+  cpu_baseline  the FP64 CPU oracle on the same tensor, timed on the host cores: the whole job
+                (T-HOSVD + the same sweeps; the precision variants add their refinement sweep)
+                for the 1080p stack, with the GPU result's errors against it (relative
+                reconstruction and core-norm differences, fit difference, largest principal-angle
+                sine per factor); T-HOSVD plus a sample of sweeps, scaled to the job, for 4K.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -94,8 +97,15 @@ def roofline_of(kind, amount, ms):
             "frac": round(achieved / peak, 4), "mfma_type": kind}
 
 
-def cpu_baseline(x32, ranks, sweeps_job, sample_sweeps):
-    """FP64 oracle on the host: T-HOSVD + `sample_sweeps` sweeps, scaled to a sweeps_job job."""
+def cpu_baseline(x32, ranks, sweeps_job, sample_sweeps, gpu_result=None, oracle_sweeps=None, start="thosvd"):
+    """FP64 oracle on the host.
+
+    sample_sweeps > 0: T-HOSVD + `sample_sweeps` sweeps, scaled to a sweeps_job job.
+    sample_sweeps == 0: the whole job (T-HOSVD + oracle_sweeps sweeps, default sweeps_job) is run and
+    timed; with gpu_result (core, factors, fit of the GPU's last decomposition, host arrays) the
+    GPU's errors against this oracle result are reported beside the time: relative reconstruction
+    difference, relative core-norm difference, fit difference and the largest principal-angle sine
+    of every factor (rotation-invariant; computed in core space)."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -103,6 +113,22 @@ def cpu_baseline(x32, ranks, sweeps_job, sample_sweeps):
     except Exception:
         cores = os.cpu_count() or 1
     x = x32.astype(np.float64)
+    if sample_sweeps == 0:
+        n_or = oracle_sweeps if oracle_sweeps is not None else sweeps_job
+        t0 = time.perf_counter()
+        o = oracle.hooi(x, ranks, n_or, start=start)
+        t_job = time.perf_counter() - t0
+        out = {"value": round(n_or / t_job, 4), "unit": "sweeps/s", "cores": cores, "kind": "oracle",
+               "sample": f"the whole job: {'T-HOSVD' if start == 'thosvd' else 'ST-HOSVD'} + {n_or} sweeps "
+                         f"of the FP64 oracle on the full tensor "
+                         f"({t_job:.2f} s)", "job_s": round(t_job, 3)}
+        if gpu_result is not None:
+            m = oracle.compare(gpu_result, dict(core=o.core, factors=o.factors, fit=o.fits[-1]))
+            out["errors_vs_oracle"] = {
+                "recon_rel": float(f"{m['recon']:.3e}"), "core_norm_rel": float(f"{m['core_norm']:.3e}"),
+                "fit_abs": float(f"{m['fit']:.3e}"), "sin_theta_max": [float(f"{v:.3e}") for v in m["sin_theta"]],
+                "oracle_fit": round(o.fits[-1], 10), "oracle_sweeps": n_or}
+        return out
     t0 = time.perf_counter()
     fac, _ = oracle.thosvd_factors(x, ranks)
     t_init = time.perf_counter() - t0
@@ -276,12 +302,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=None, help="sweeps per decomposition (default: the workload's)")
-    ap.add_argument("--cpu-sample-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sample-sweeps", type=int, default=None,
+                    help="oracle sweeps timed for the CPU baseline and scaled to the job; 0 runs the whole "
+                         "oracle job and reports the GPU result's errors against it (default: 0 for "
+                         "stack1080, 2 for stack2160)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="stack1080", choices=["stack1080", "stack2160"],
                     help="stack1080: 1080p Y'CbCr, 20 sweeps (the default measurement); stack2160: 4K IPT, 15 sweeps")
     ap.add_argument("--init-iters", type=int, default=20,
                     help="cold-start orthogonal-iteration steps of the T-HOSVD start")
+    ap.add_argument("--start", default="thosvd", choices=["thosvd", "sthosvd"],
+                    help="initialisation: truncated HOSVD (default) or the sequentially truncated HOSVD")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
     ap.add_argument("--graphs", action="store_true",
@@ -322,9 +353,10 @@ def main():
     if args.graphs:
         side = torch.cuda.Stream()
         ctx = tk.Context(0, stream=side, timing=False, precision=args.precision, refine_sweeps=1,
-                         init_iters=args.init_iters, use_graphs=True)
+                         init_iters=args.init_iters, use_graphs=True, start=args.start)
     else:
-        ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters)
+        ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters,
+                         start=args.start)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
@@ -383,7 +415,8 @@ def main():
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16", "fp8": "fp8_e4m3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {H}x{W}x3x{2 * E} FP32 {cfg['colorspace']} multi-exposure stereo stack, ranks "
-                               f"{list(ranks)}, T-HOSVD start + {sweeps} HOOI sweeps per step"
+                               f"{list(ranks)}, {'T-HOSVD' if args.start == 'thosvd' else 'ST-HOSVD'} start + "
+                               f"{sweeps} HOOI sweeps per step"
                                + ("" if args.precision == "fp32" else
                                   f" ({args.precision} contractions, then 1 FP32 refinement sweep)"),
                    "precision": args.precision,
@@ -393,10 +426,17 @@ def main():
         "roofline": roof,
         "stages": stages,
     }
+    gpu_result = dict(core=r.core.cpu().numpy().astype(np.float64),
+                      factors=[u.cpu().numpy().astype(np.float64) for u in r.factors], fit=r.fit)
     ctx.close()
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(x32, ranks, sweeps, args.cpu_sample_sweeps)
+        sample = args.cpu_sample_sweeps
+        if sample is None:
+            sample = 0 if args.workload == "stack1080" else 2
+        log("timing the CPU oracle" + (" (whole job, errors of the GPU result against it)" if sample == 0 else
+                                       " sample"))
+        refine = 0 if args.precision == "fp32" else 1
+        out["cpu_baseline"] = cpu_baseline(x32, ranks, sweeps, sample, gpu_result, sweeps + refine, args.start)
     print(json.dumps(out), flush=True)
 
 

@@ -65,20 +65,42 @@ typedef enum {
     TUCKER_FP8_E4M3 = 3
 } tucker_precision;
 
+/* How the factors are initialised (Sec. III-B.1). */
+typedef enum {
+    TUCKER_START_THOSVD = 0,     /* truncated HOSVD: U_n = leading R_n eigenvectors of X_(n) X_(n)^T,
+                                    every mode from the unprojected tensor (eq. (6)-(7))      */
+    TUCKER_START_STHOSVD = 1     /* sequentially truncated ("interlaced") HOSVD, the cheaper start
+                                    named after eq. (7): modes in ascending order, U_n from the
+                                    Gram of X x_1 U_1^T ... x_{n-1} U_{n-1}^T                  */
+} tucker_start;
+
 typedef struct {
     int device;                  /* HIP device ordinal                                        */
     void* stream;                /* hipStream_t owned by the caller; NULL = default stream    */
     tucker_precision precision;  /* contraction operand precision of the sweeps               */
     int refine_sweeps;           /* FP32 sweeps appended after reduced-precision sweeps       */
-    int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1)   */
-    int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD     */
-    double inner_tol;            /* reserved (0)                                              */
+    int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1);
+                                    with inner_tol > 0, the most steps an update may take     */
+    int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD;
+                                    with inner_tol > 0, the most steps a start may take       */
+    double inner_tol;            /* 0: fixed step counts.  > 0: each large-mode update, cold or
+                                    warm, forms its Gram S and iterates until the invariant-
+                                    subspace residual ||S U - U (U^T S U)||_F <= inner_tol ||S||_F
+                                    (checked on the host after every step, so sweeps are then
+                                    launched one kernel at a time); steps taken are reported in
+                                    tucker_stats                                               */
     int use_graphs;              /* 1: capture one sweep as a HIP graph and replay it for every
                                     sweep (needs a non-NULL stream, timing 0 and tol 0; otherwise
                                     the sweeps are launched one kernel at a time)              */
     size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
     uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
     int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats)   */
+    int64_t wait_spin_limit;     /* bound of every wait inside the Cholesky task graph, in sleep
+                                    steps of about 64 cycles; 0 = the default (2^24, about half
+                                    a second).  A wait that reaches it gives up, the kernel
+                                    finishes normally and the call returns TUCKER_ERR_DEVICE.
+                                    Tiny values exist to exercise that error path.            */
+    tucker_start start;          /* initialisation of the factors (default TUCKER_START_THOSVD) */
 } tucker_options;
 
 /* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack
@@ -111,6 +133,12 @@ typedef struct {
     int chol_shifts;             /* Cholesky pivots that needed the shifted fallback          */
     int orth_second_passes;      /* CholeskyQR passes run because one pass left ||Q^T Q - I||
                                     above the FP64 threshold (the rest were skipped on device) */
+    int wait_timeouts;           /* Cholesky task-graph calls in which a wait gave up (the call
+                                    then returned TUCKER_ERR_DEVICE)                           */
+    int oi_steps_init;           /* orthogonal-iteration steps of the start (all large modes) */
+    int oi_steps_sweeps;         /* orthogonal-iteration steps of the sweeps (all large modes) */
+    double oi_residual_max;      /* inner_tol > 0: largest final ||S U - U U^T S U||_F / ||S||_F
+                                    over the updates of the call (0 otherwise)                */
     size_t workspace_bytes;      /* device workspace held by the context                      */
     double stage_ms[TUCKER_NUM_STAGES];   /* summed GPU time per stage (timing = 1)           */
     int stage_calls[TUCKER_NUM_STAGES];   /* number of timed occurrences per stage            */
@@ -141,7 +169,7 @@ tucker_status tucker_destroy(tucker_ctx* ctx);
 /* Tucker decomposition by HOOI (T-HOSVD start, then up to max_iters sweeps).
  *   tensor   device, prod(dims) floats, read-only.
  *   dims     host, ndim entries; ranks host, ndim entries.
- *   max_iters number of sweeps; 0 returns the T-HOSVD result.
+ *   max_iters number of sweeps; 0 returns the start (T-HOSVD, or ST-HOSVD per tucker_options.start).
  *   tol      stop early when |fit_k - fit_{k-1}| < tol (tol = 0: run all sweeps).  With tol > 0
  *            each sweep's fit is the explicit residual fit (one more expanding pass per sweep);
  *            with tol = 0 it is the cheaper 1 - sqrt(||X||^2 - ||G||^2) / ||X|| from the FP32 core,
@@ -210,8 +238,11 @@ tucker_status tucker_gram_lowp(tucker_ctx* ctx, const float* in, int ndim, const
                                int mode, tucker_precision precision, float* out);
 
 /* Orthonormal basis of the column space of Z (rows x cols, rows >= cols) by FP64
- * CholeskyQR2 with column scaling.  Z, Q device floats, row-major; Q may alias Z.
- * Stream-ordered. */
+ * CholeskyQR with column scaling: one shifted pass, then two plain ones (shifted CholeskyQR3),
+ * the orthogonalisation step of orthogonal iteration (the text after eq. (8)).  Z, Q device
+ * floats, row-major; Q may alias Z.  Pivots that needed the shifted fallback are counted in
+ * tucker_stats.chol_shifts.  Synchronises the stream: TUCKER_ERR_DEVICE when a wait of the
+ * Cholesky task graph gave up (tucker_options.wait_spin_limit). */
 tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols,
                                     float* Q);
 
@@ -222,8 +253,9 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
  *                     D = diag(W)^(1/2), D^-1 W D^-1 = L L^T, writes T = L^-1 D^-1 (lower triangular,
  *                     upper part zero) to T (device n x n doubles); Z T^T then has orthonormal
  *                     columns.  Pivots that are not safely positive are shifted and counted in
- *                     tucker_stats.chol_shifts.
- * Both stream-ordered. */
+ *                     tucker_stats.chol_shifts.  Synchronises the stream; TUCKER_ERR_DEVICE when
+ *                     a wait of the task graph gave up (tucker_options.wait_spin_limit).
+ * tucker_gram_tn64 is stream-ordered. */
 tucker_status tucker_gram_tn64(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols, double* W);
 tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, double* T);
 

@@ -16,6 +16,7 @@ from .hooi_ref import (  # noqa: F401
     project_all_but,
     reconstruct,
     sign_fix,
+    st_hosvd_factors,
     thosvd_factors,
     ttm,
     unfold,

@@ -12,6 +12,9 @@ Paper passages followed (Sharma & Grover, arXiv 2104.04726):
 * T-HOSVD initialisation, Sec. III-B.1, eq. (3)-(7): the kept factor of mode r is the
   block of leading k_r left singular vectors of the mode-r unfolding of the data tensor
   (eq. (6)), and the truncated core is the data projected on those bases (eq. (7)).
+  The interlaced HOSVD that the same section offers as a cheaper start is read as the
+  sequentially truncated HOSVD: each mode's factor from the tensor already projected on the
+  earlier modes' factors.
 * HOOI sweep, Sec. III-B, eq. (8): for each mode n, Y(n) = X x_{m != n} S(m)^T, then S(n)
   takes the R_n leading left singular vectors of Y(n)_(n), obtained as the leading
   eigenvectors of the Gram matrix Y(n)_(n) Y(n)_(n)^T (the text right after eq. (8)).
@@ -158,6 +161,29 @@ def thosvd_factors(x: np.ndarray, ranks):
     return factors, spectra
 
 
+def st_hosvd_factors(x: np.ndarray, ranks):
+    """Sequentially truncated ("interlaced") HOSVD, the cheaper start the paper names after eq. (7).
+
+    Modes are taken in ascending order.  S(n) = leading R_n left singular vectors of the mode-n
+    unfolding of the tensor already projected on the earlier factors,
+    Y(n-1) = X x_1 S(1)^T ... x_{n-1} S(n-1)^T (via its Gram), and Y(n) = Y(n-1) x_n S(n)^T; the
+    core of the start is Y(N).  Returns (factors, spectra, core) with spectra[n] the eigenvalues of
+    the Gram of Y(n-1)_(n), descending.  R_n = s_n keeps the identity basis: it spans all of R^{s_n}.
+    """
+    y = x
+    factors, spectra = [], []
+    for n, r in enumerate(ranks):
+        s_n = gram(y, n)
+        if r == x.shape[n]:
+            u, lam = np.eye(r), np.linalg.eigvalsh(s_n)[::-1]
+        else:
+            u, lam = leading_eigvecs(s_n, r)
+        factors.append(u)
+        spectra.append(lam)
+        y = ttm(y, u.T, n)
+    return factors, spectra, y
+
+
 def hooi_update(x: np.ndarray, factors, n: int, rank: int):
     """One factor update of eq. (8): Y = X x_{m != n} S(m)^T, S(n) <- top-R_n eigvecs of Y_(n)Y_(n)^T.
 
@@ -189,20 +215,27 @@ class HooiResult:
         return float(lam[0] / gap) if gap > 0 else math.inf
 
 
-def hooi(x: np.ndarray, ranks, max_iters: int = 10, tol: float = 0.0, init=None) -> HooiResult:
+def hooi(x: np.ndarray, ranks, max_iters: int = 10, tol: float = 0.0, init=None,
+         start: str = "thosvd") -> HooiResult:
     """Tucker-ALS by HOOI, FP64.
 
-    init: optional list of orthonormal factors replacing the T-HOSVD start (resume).
+    init: optional list of orthonormal factors replacing the start (resume).
+    start: "thosvd" (every factor from the unprojected X, Sec. III-B.1) or "sthosvd" (the
+    sequentially truncated / interlaced HOSVD, st_hosvd_factors).
     """
     x = np.asarray(x, dtype=np.float64)
     ranks = [int(r) for r in ranks]
     validate(x.shape, ranks, max_iters, tol)
+    if start not in ("thosvd", "sthosvd"):
+        raise ValueError("start must be 'thosvd' or 'sthosvd'")
     nx2 = float(np.sum(x * x))
     if nx2 == 0.0:
         factors = identity_factors(x.shape, ranks)
         return HooiResult(np.zeros(ranks), factors, [1.0], 0, 0.0,
                           [np.zeros(s) for s in x.shape])
-    if init is None:
+    if init is None and start == "sthosvd":
+        factors, spectra, _ = st_hosvd_factors(x, ranks)
+    elif init is None:
         factors, spectra = thosvd_factors(x, ranks)
     else:
         factors = [np.array(u, dtype=np.float64, copy=True) for u in init]

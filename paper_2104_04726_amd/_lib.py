@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "tucker.h")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERICAL, ERR_UNSUPPORTED, ERR_TIMEOUT = range(7)
 FP32, BF16, FP16, FP8_E4M3 = range(4)
+START_THOSVD, START_STHOSVD = range(2)
 
 
 class Options(C.Structure):
@@ -31,6 +32,8 @@ class Options(C.Structure):
         ("hbm_budget_bytes", C.c_size_t),
         ("seed", C.c_uint64),
         ("timing", C.c_int),
+        ("wait_spin_limit", C.c_int64),
+        ("start", C.c_int),
     ]
 
 
@@ -44,6 +47,10 @@ class Stats(C.Structure):
         ("refine_sweeps", C.c_int),
         ("chol_shifts", C.c_int),
         ("orth_second_passes", C.c_int),
+        ("wait_timeouts", C.c_int),
+        ("oi_steps_init", C.c_int),
+        ("oi_steps_sweeps", C.c_int),
+        ("oi_residual_max", C.c_double),
         ("workspace_bytes", C.c_size_t),
         ("stage_ms", C.c_double * 12),
         ("stage_calls", C.c_int * 12),
@@ -159,7 +166,8 @@ def _declare(lib):
     for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
                  "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
                  "tucker_quantize", "tucker_ttm_lowp", "tucker_gram_lowp",
-                 "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv", "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):
+                 "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv",
+                 "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):
         getattr(lib, name).restype = C.c_int
 
 

@@ -37,6 +37,8 @@ hipError_t tk_set_int(int* p, int v, hipStream_t s);
 hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_t s);
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
                           hipStream_t s);
+hipError_t tk_diff_sumsq_f64(const double* A, const double* B, int64_t n, double* partial, int nblocks, double* out,
+                             hipStream_t s);
 
 struct tucker_ctx {
     int device = 0;
@@ -390,6 +392,11 @@ struct Run {
     size_t next_ev = 0;
     int inner_override = 0;     // orthogonal-iteration steps per update in refinement sweeps
     double orth_tol = 1e-12;    // CholeskyQR second-pass threshold on max |Q^T Q - I|
+    int oi_steps_init = 0, oi_steps_sweeps = 0;   // orthogonal-iteration steps taken (host count)
+    double oi_resid_max = 0.0;  // inner_tol > 0: largest final relative residual of an update
+
+    long long spin() const { return (long long)ctx->opt.wait_spin_limit; }
+    double inner_tol() const { return ctx->opt.inner_tol; }
 
     int record() {
         if (next_ev >= ctx->pool.size()) {
@@ -627,7 +634,8 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
         // an intermediate step of the cold start: one CholeskyQR pass gives a basis of span(Z),
         // all that the next product S U needs; the last step delivers the orthonormal factor
         gram_tn64(r, Z, z32, rows, cols, p.W, true);
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st,
+                               nullptr, r.spin()));
         apply_tri(r, Z, z32, rows, cols, p.Tm, U64);
         return;
     }
@@ -635,29 +643,66 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
     const double shift = cold ? 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) * u * (double)cols : 0.0;
     // pass 1: Z -> Q1
     gram_tn64(r, Z, z32, rows, cols, p.W, true);
-    TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
+    TK_HIP(chol_inv_scaled(p.W, cols, true, shift, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st,
+                               nullptr, r.spin()));
     apply_tri(r, Z, z32, rows, cols, p.Tm, p.Q1);
     gram_tn64(r, p.Q1, false, rows, cols, p.W, true);
     if (!cold) {
         // pass 2 only where needed: need = p.shifts[2], counted in p.shifts[1]
         int* need = p.shifts + 2;
         TK_HIP(orth_check(p.W, cols, r.orth_tol, p.red, need, p.shifts + 1, p.shifts + 4, r.st));
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st, need));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st,
+                               need, r.spin()));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64, need);
         TK_HIP(finish_factor(need, p.Q1, U64, U32, rows * cols, r.st));
         return;
     } else {
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st,
+                               nullptr, r.spin()));
         apply_tri(r, p.Q1, false, rows, cols, p.Tm, U64);
         gram_tn64(r, U64, false, rows, cols, p.W, true);
-        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st));
+        TK_HIP(chol_inv_scaled(p.W, cols, true, 0.0, p.Tm, (int*)p.chol_ws, p.chol_dsc, p.shifts, r.st,
+                               nullptr, r.spin()));
         apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
         TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
     }
     TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
 }
 
-// q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR
+// ||Z - U (U^T Z)||_F for Z = S U in p.Z (s x R) and orthonormal U (FP64): the residual of span(U) as an
+// invariant subspace of S.  B = U^T Z goes to p.W, Z - U B to p.Q1; synchronises the stream.
+double subspace_residual(Run& r, const double* U, int64_t s, int64_t R) {
+    Plan& p = r.p;
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = R;
+    g.N = R;
+    g.K = s;
+    g.a = plain(U, R);          // A(m, k) = U[k][m]
+    g.b = plain(p.Z, R);        // B(k, n) = Z[k][n]
+    g.c = plain(p.W, R);
+    g.k_split = s;
+    TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+    GemmArgs h{};
+    h.alpha = 1.0;
+    h.M = s;
+    h.N = R;
+    h.K = R;
+    h.a = plain(U, R);          // A(m, k) = U[m][k]
+    h.b = plain(p.W, R);        // B(k, n) = B[k][n]
+    h.c = plain(p.Q1, R);
+    h.k_split = R;
+    TK_HIP(gemm_f64(h, MK, KM, EPI_STORE, false, false, r.st));
+    double e2 = 0.0;
+    TK_HIP(tk_diff_sumsq_f64(p.Z, p.Q1, s * R, p.red, kSumsqBlocks - 8, p.red + kSumsqBlocks - 3, r.st));
+    TK_HIP(hipMemcpyAsync(&e2, p.red + kSumsqBlocks - 3, sizeof(double), hipMemcpyDeviceToHost, r.st));
+    TK_HIP(hipStreamSynchronize(r.st));
+    return std::sqrt(e2);
+}
+
+// q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR.  With
+// inner_tol > 0, q is the most steps, and the iteration stops once span(U) is invariant to the
+// tolerance (checked once more after the q-th step)
 void orth_iter(Run& r, int n, int q, bool cold) {
     Plan& p = r.p;
     const int64_t s = p.s[n], R = p.R[n];
@@ -684,7 +729,17 @@ void orth_iter(Run& r, int n, int q, bool cold) {
     int64_t ks = (s + splits - 1) / splits;
     ks = (ks + 15) / 16 * 16;
     const int nsplit = (int)((s + ks - 1) / ks);
-    for (int it = 0; it < q; ++it) {
+    // inner_tol > 0: ||S||_F once; each step's product Z = S U first measures the residual of the
+    // current U, and the iteration stops there when it is small enough
+    const double tol = r.inner_tol();
+    double snorm = 0.0, resid = -1.0;
+    if (tol > 0.0) {
+        TK_HIP(sumsq_f64(p.S64, s * s, p.red, kSumsqBlocks - 8, p.red + kSumsqBlocks - 4, r.st));
+        TK_HIP(hipMemcpyAsync(&snorm, p.red + kSumsqBlocks - 4, sizeof(double), hipMemcpyDeviceToHost, r.st));
+        TK_HIP(hipStreamSynchronize(r.st));
+        snorm = std::sqrt(snorm);
+    }
+    for (int it = 0; it < q || (tol > 0.0 && it == q); ++it) {
         GemmArgs g{};
         g.alpha = 1.0;
         g.M = s;
@@ -702,11 +757,18 @@ void orth_iter(Run& r, int n, int q, bool cold) {
             g.c = plain(p.Z, R);
             TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
         }
+        if (tol > 0.0 && !(cold && it == 0)) {
+            resid = subspace_residual(r, p.U64[n], s, R) / std::max(snorm, 1e-300);
+            if (resid <= tol || it == q) break;
+        }
         // cold start: shifted CholeskyQR3 for the first two steps, one pass for the intermediate
-        // ones (U32 = nullptr), the checked CholeskyQR2 for the last
-        const bool mid = cold && it >= 2 && it < q - 1;
+        // ones (U32 = nullptr), the checked CholeskyQR2 for the last; with a tolerance every step
+        // may be the last, so every step after the first two is a checked CholeskyQR2
+        const bool mid = cold && it >= 2 && it < q - 1 && tol <= 0.0;
         orthonormalize(r, p.Z, false, s, R, p.U64[n], mid ? nullptr : p.U32[n], cold && it < 2);
+        (cold ? r.oi_steps_init : r.oi_steps_sweeps) += 1;
     }
+    if (tol > 0.0) r.oi_resid_max = std::max(r.oi_resid_max, resid);
 }
 
 // factor update of mode n from the Gram in S64
@@ -740,7 +802,8 @@ void update_factor(Run& r, int n, bool cold) {
 // vector-load FP32-operand kernels.  Used when one step per sweep is asked for.
 bool direct_update_ok(const Run& r, int n) {
     const Plan& p = r.p;
-    return p.tree && p.kind[n] == LARGE && r.inner_override <= 0 && r.ctx->opt.inner_iters == 1;
+    return p.tree && p.kind[n] == LARGE && r.inner_override <= 0 && r.ctx->opt.inner_iters == 1 &&
+           !(r.inner_tol() > 0.0);
 }
 
 // The W product of a one-step update: W = Uw^T Yw with Uw (K x Rw, FP32 factor, m = r contiguous)
@@ -887,7 +950,8 @@ void thosvd(Run& r) {
             update_factor(r, n, true);
         }
     };
-    if (!p.has_alt) {
+    if (!p.has_alt || r.inner_tol() > 0.0) {
+        // (with a tolerance every step waits for the host, so the two streams could not overlap)
         modes_from(0);
         return;
     }
@@ -908,6 +972,66 @@ void thosvd(Run& r) {
     modes_from(2);
     swap_oi(p);
     join_aux(r);
+}
+
+// ------------------------------------------------------------------ ST-HOSVD initialisation
+// The sequentially truncated ("interlaced") HOSVD, the cheaper start of Sec. III-B.1: modes in
+// ascending order, each factor from the Gram of the tensor already projected on the earlier
+// factors, Y(n) = Y(n-1) x_n U_n^T; the last projection is the core.  Tree shapes reuse the sweep's
+// buffers: T1 = X x_1 U1^T (pass C1) feeds mode 2's Gram (contracted over R1 s3 s4 instead of
+// s1 s3 s4), T12 = T1 x_2 U2^T feeds the fibre Gram of the two small modes, and G closes the start.
+// Leaves the core in p.G.
+void sthosvd(Run& r) {
+    Plan& p = r.p;
+    const int N = p.N;
+    auto start_mode = [&](const float* y, const int64_t* d, int nd, int n) {
+        if (p.kind[n] == FIXED) {
+            identity_factor(r, n);
+            return;
+        }
+        gram(r, y, d, nd, n);
+        update_factor(r, n, true);
+    };
+    if (p.tree) {
+        const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3], L = s2 * s3;
+        int64_t d[3] = {s0, s1, L};
+        start_mode(r.X, d, 3, 0);
+        ttm(r, r.X, d, 3, 0, p.U32[0], p.R[0], false, p.T1);
+        d[0] = p.R[0];
+        start_mode(p.T1, d, 3, 1);
+        ttm(r, p.T1, d, 3, 1, p.U32[1], p.R[1], false, p.T12);
+        // modes 3 and 4 from the fibre Gram of T12: mode 3 with mode 4 not yet projected, then
+        // mode 4 with mode 3 projected on the new U3
+        TK_HIP(fibre_gram(p.T12, p.R[0] * p.R[1], (int)L, p.Fpart, kFibreGramBlocks, p.F, r.st));
+        if (p.kind[2] == FIXED) {
+            identity_factor(r, 2);
+        } else {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, nullptr, 0, 3, p.S64, r.st));
+            update_factor(r, 2, true);
+        }
+        if (p.kind[3] == FIXED) {
+            identity_factor(r, 3);
+        } else {
+            TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[2], (int)p.R[2], 4, p.S64, r.st));
+            update_factor(r, 3, true);
+        }
+        TK_HIP(pair_ttm(p.T12, p.R[0] * p.R[1], (int)s2, (int)s3, p.U32[2], (int)p.R[2], p.U32[3], (int)p.R[3],
+                        false, p.G, r.st));
+        return;
+    }
+    int64_t d[TUCKER_MAX_ORDER];
+    for (int i = 0; i < N; ++i) d[i] = p.s[i];
+    const float* cur = r.X;
+    float* bufs[2] = {p.Ya, p.Yb};
+    int w = 0;
+    for (int n = 0; n < N; ++n) {
+        start_mode(cur, d, N, n);
+        float* dst = (n == N - 1) ? p.G : bufs[w];
+        ttm(r, cur, d, N, n, p.U32[n], p.R[n], false, dst);
+        d[n] = p.R[n];
+        cur = dst;
+        w ^= 1;
+    }
 }
 
 // ------------------------------------------------------------------ one ALS sweep
@@ -1365,6 +1489,22 @@ __global__ void resid_kernel(const float* __restrict__ X, const float* __restric
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
+__global__ void diff_sumsq64_kernel(const double* __restrict__ A, const double* __restrict__ B, int64_t n,
+                                    double* __restrict__ partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = A[i] - B[i];
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
 }  // namespace
 
 hipError_t tk_set_int(int* p, int v, hipStream_t s) {
@@ -1392,6 +1532,14 @@ hipError_t tk_sum_splits_to_f32(const double* P, int nsplit, int64_t n, int64_t 
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
                           hipStream_t s) {
     hipLaunchKernelGGL(resid_kernel, dim3(nblocks), dim3(256), 0, s, X, Xh, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_f64(partial, nblocks, out, s);
+}
+
+hipError_t tk_diff_sumsq_f64(const double* A, const double* B, int64_t n, double* partial, int nblocks, double* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(diff_sumsq64_kernel, dim3(nblocks), dim3(256), 0, s, A, B, n, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_f64(partial, nblocks, out, s);
@@ -1437,6 +1585,19 @@ void with_scratch(tucker_ctx* ctx, Fn layout) {
     b.base = (char*)ctx->ws;
     b.cap = ctx->ws_bytes;
     layout(b);
+}
+
+// After a step-level call that ran the Cholesky task graph: synchronise, record the pivot shifts and
+// timed-out waits (int counters as laid out by chol_inv_scaled) and fail when a wait gave up.
+void check_chol_calls(tucker_ctx* ctx, const int* shifts, hipStream_t s) {
+    int h[8] = {};
+    TK_HIP(hipMemcpyAsync(h, shifts, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    ctx->stats.chol_shifts = h[0];
+    ctx->stats.wait_timeouts = h[kWaitTimeoutSlot];
+    if (h[kWaitTimeoutSlot])
+        throw Fail{TUCKER_ERR_DEVICE, "Cholesky task graph: a wait gave up (wait_spin_limit reached); the result is "
+                                      "invalid"};
 }
 
 }  // namespace
@@ -1486,7 +1647,8 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
     tucker_default_options(&o);
     if (opts) o = *opts;
     if (o.inner_iters < 1 || o.init_iters < 1 || o.refine_sweeps < 0 || o.precision < TUCKER_FP32 ||
-        o.precision > TUCKER_FP8_E4M3 || o.device < 0)
+        o.precision > TUCKER_FP8_E4M3 || o.device < 0 || !(o.inner_tol >= 0.0) || o.wait_spin_limit < 0 ||
+        (o.start != TUCKER_START_THOSVD && o.start != TUCKER_START_STHOSVD))
         return TUCKER_ERR_INVALID_ARG;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
@@ -1514,6 +1676,7 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
         tucker_destroy(c);
         return TUCKER_ERR_DEVICE;
     }
@@ -1566,6 +1729,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
     return guarded(ctx, [&]() {
         Run r{ctx, Plan{}, ctx->stream, tensor};
         Plan& p = r.p;
+        ctx->stats = tucker_stats{};
         make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps);
         bind(ctx, p);
         const hipStream_t s = r.st;
@@ -1594,6 +1758,8 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
                                       hipMemcpyDeviceToDevice, s));
                 TK_HIP(f32_to_f64(p.U32[n], p.U64[n], p.s[n] * p.R[n], s));
             }
+        } else if (ctx->opt.start == TUCKER_START_STHOSVD) {
+            sthosvd(r);
         } else {
             thosvd(r);
         }
@@ -1609,7 +1775,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
                 core_norm_and_fit(r, slot);
             }
         };
-        core_from_x(r);
+        if (init_factors || ctx->opt.start != TUCKER_START_STHOSVD) core_from_x(r);   // (ST-HOSVD ends with G)
         sweep_fit(p.fits + 0);
         TK_HIP(hipEventRecord(ctx->ev[1], s));
         int done = 0;
@@ -1630,7 +1796,8 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         // max_iters times; every node reads and writes the same workspace each sweep, and the fit
         // lands in fits[k] through a device-side counter.  Needs a capturable (non-null) stream,
         // no per-sweep host read (tol = 0) and no stage timers.
-        const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0;
+        const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0 &&
+                            !(r.inner_tol() > 0.0);
         GraphHold hold{s};
         if (graphs) {
             TK_HIP(tk_set_int(p.shifts + 3, 1, s));
@@ -1683,10 +1850,15 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         double fexact = 0.0;
         TK_HIP(hipMemcpyAsync(fits.data(), p.fits, (total + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         TK_HIP(hipMemcpyAsync(&fexact, p.scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-        int shifts2[4] = {0, 0, 0, 0}, shifts3[4] = {0, 0, 0, 0};
-        TK_HIP(hipMemcpyAsync(shifts2, p.shifts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-        if (p.has_alt) TK_HIP(hipMemcpyAsync(shifts3, p.shiftsb, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        int shifts2[8] = {}, shifts3[8] = {};
+        TK_HIP(hipMemcpyAsync(shifts2, p.shifts, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (p.has_alt) TK_HIP(hipMemcpyAsync(shifts3, p.shiftsb, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
+        ctx->stats.wait_timeouts = shifts2[kWaitTimeoutSlot] + shifts3[kWaitTimeoutSlot];
+        if (ctx->stats.wait_timeouts)
+            throw Fail{TUCKER_ERR_DEVICE, "Cholesky task graph: a wait gave up in " +
+                                              std::to_string(ctx->stats.wait_timeouts) +
+                                              " call(s) (wait_spin_limit reached); the factors are invalid"};
         *fit = fexact;
         if (fit_history)
             for (int k = 0; k <= done; ++k) fit_history[k] = fits[k];
@@ -1707,6 +1879,9 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         ctx->stats.refine_sweeps = p.refine;
         ctx->stats.chol_shifts = shifts2[0] + shifts3[0];
         ctx->stats.orth_second_passes = shifts2[1] + shifts3[1];
+        ctx->stats.oi_steps_init = r.oi_steps_init;
+        ctx->stats.oi_steps_sweeps = r.oi_steps_sweeps;
+        ctx->stats.oi_residual_max = r.oi_resid_max;
         ctx->stats.workspace_bytes = ctx->ws_bytes;
         if (!std::isfinite(fexact)) throw Fail{TUCKER_ERR_NUMERICAL, "non-finite fit"};
     });
@@ -1899,6 +2074,7 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
         });
         reset_counters(r);
         orthonormalize(r, Z, true, rows, cols, U64, Q, true);
+        check_chol_calls(ctx, p.shifts, r.st);
     });
 }
 
@@ -1928,16 +2104,14 @@ tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, doubl
             Wc = a.take<double>(n * n);
             cw = a.take<int>(chol_counter_ints(n));
             dsc = a.take<double>(n);
-            shifts = a.take<int>(4);
+            shifts = a.take<int>(8);
         });
-        TK_HIP(fill_zero(shifts, 16, ctx->stream));
+        TK_HIP(fill_zero(shifts, 8 * sizeof(int), ctx->stream));
         TK_HIP(fill_zero(cw, chol_counter_ints(n) * (int64_t)sizeof(int), ctx->stream));
         TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, cw, dsc, shifts, ctx->stream));
-        int sh = 0;
-        TK_HIP(hipMemcpyAsync(&sh, shifts, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        TK_HIP(hipStreamSynchronize(ctx->stream));
-        ctx->stats.chol_shifts = sh;
+        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, cw, dsc, shifts, ctx->stream, nullptr,
+                               (long long)ctx->opt.wait_spin_limit));
+        check_chol_calls(ctx, shifts, ctx->stream);
     });
 }
 

@@ -130,10 +130,15 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // triangular) to Tout.  W's off-diagonal tiles are overwritten by L; its diagonal tiles are kept.
 // counters: chol_counter_ints(n) ints that must be zero on entry; they are zero again when the
 // call's kernels have finished.  dsc: n doubles of scratch (the diagonal scale).
-// shifts: int counter incremented for every pivot that needed the shifted fallback.
+// shifts: at least kWaitTimeoutSlot + 1 ints; shifts[0] is incremented for every pivot that needed
+// the shifted fallback, shifts[kWaitTimeoutSlot] for every call in which a wait of the task graph
+// gave up after max_spin sleep steps (<= 0: the default bound, about half a second); such a call's
+// result is garbage and the caller must report an error.
 // run_if (nullable): every kernel of the call returns at once when *run_if == 0.
+constexpr int kWaitTimeoutSlot = 5;
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           double* dsc, int* shifts, hipStream_t s, const int* run_if = nullptr);
+                           double* dsc, int* shifts, hipStream_t s, const int* run_if = nullptr,
+                           long long max_spin = 0);
 // need[0] = 1 (and ++count[0]) when max_{i>=j} |W_ij - delta_ij| > tol, else 0 (n x n FP64, symmetric:
 // only the lower triangle is read), in one
 // launch.  partial: orth_check_partials() doubles of scratch; sync: an int that is zero on entry

@@ -8,9 +8,10 @@
 //   and applies its update from LDS, so the critical path crosses one flag per column.
 //   Each workgroup claims the next task with an atomic ticket, so every task it waits for was
 //   claimed earlier by a running workgroup: the graph cannot deadlock whatever the residency.
-//   Waits are bounded spins; a timeout raises an error flag instead of hanging.
-//   Producer: coherent stores, wait for their completion, barrier, coherent flag store.
-//   Consumer: coherent flag load, barrier, coherent loads.
+//   Waits are bounded spins; a wait that gives up raises an error flag instead of hanging, and the
+//   epilogue counts it in a word the host reads back (the call then fails with a device error).
+//   Producer: coherent stores, barrier, agent-scope release store of the flag.
+//   Consumer: agent-scope acquire load of the flag, barrier, coherent loads.
 //
 // jacobi_eig: cyclic two-sided Jacobi (Golub & Van Loan, Alg. 8.4.3, with the parallel
 //   round-robin ordering) on a symmetric matrix of order <= 64 held in LDS.
@@ -28,7 +29,7 @@ namespace {
 constexpr int TB = TK_CHOL_TB;
 constexpr int TS = TB + 1;                  // padded LDS row stride
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
-constexpr long long kMaxSpin = 1ll << 24;   // bounded waits (x ~64 cycles of sleep each)
+constexpr long long kMaxSpin = 1ll << 24;   // default bound of a wait (x ~64 cycles of sleep each)
 
 struct CholArgs {
     double* W;
@@ -44,17 +45,19 @@ struct CholArgs {
     int* shifts;
     int* err;
     const int* run_if;
+    long long max_spin;    // bound of every wait, in sleep steps
 };
 
-// Shared tiles and flags are accessed with agent-scope relaxed atomics, which are coherent across
-// the XCDs without whole-L2 writeback/invalidate.  A producer waits for its stores to complete
-// (vmcnt 0) before the workgroup barrier that precedes the flag store; a consumer issues its tile
-// loads only after observing the flag.
+// Shared tiles are accessed with agent-scope relaxed atomics, which are coherent across the XCDs.
+// Flags carry the ordering: the producer's tile stores happen before the workgroup barrier, which
+// happens before thread 0's agent-scope release store of the flag; the consumer's thread 0 reads
+// the flag with an agent-scope acquire load, and the barrier after it orders every thread's tile
+// loads after that acquire.
 __device__ __forceinline__ int ld_flag(int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_flag(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_coh(const double* p) {
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -68,14 +71,15 @@ __device__ __forceinline__ void stores_done() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ void wait_flags(int* f1, int* f2, int* err) {
+__device__ void wait_flags(int* f1, int* f2, int* err, long long max_spin) {
     if (threadIdx.x == 0) {
         long long it = 0;
-        while ((ld_flag(f1) == 0 || (f2 && ld_flag(f2) == 0)) && it < kMaxSpin) {
+        bool ready;
+        while (!(ready = (ld_flag(f1) != 0 && (!f2 || ld_flag(f2) != 0))) && it < max_spin) {
             __builtin_amdgcn_s_sleep(1);
             ++it;
         }
-        if (it >= kMaxSpin) st_flag(err, 1);
+        if (!ready) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __syncthreads();
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
         if (sub) {
             // A_jj -= L_jk L_jk^T and A_j,j-1 -= L_jk L_j-1,k^T for k < j - 1
             for (int k = 0; k < j - 1; ++k) {
-                wait_flags(fL(j, k), fL(j - 1, k), a.err);
+                wait_flags(fL(j, k), fL(j - 1, k), a.err, a.max_spin);
                 load_tile(a.W, a.n, j, k, Bt, nullptr, nullptr, false);
                 load_tile(a.W, a.n, j - 1, k, Dt, nullptr, nullptr, false);
                 __syncthreads();
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
                 tile_gemm(Ct, Bt, Dt, true, -1.0, 1.0);
             }
             // L_j,j-1 = A_j,j-1 Linv_j-1^T, published at once; then A_jj -= L_j,j-1 L_j,j-1^T from LDS
-            wait_flags(fI(j - 1, j - 1), nullptr, a.err);
+            wait_flags(fI(j - 1, j - 1), nullptr, a.err, a.max_spin);
             load_tile(a.Tout, a.n, j - 1, j - 1, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Dt, Ct, Bt, true, 1.0, 0.0);
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
             tile_gemm(At, Dt, Dt, true, -1.0, 1.0);
         } else {
             for (int k = 0; k < j; ++k) {
-                wait_flags(fL(i, k), fL(j, k), a.err);
+                wait_flags(fL(i, k), fL(j, k), a.err, a.max_spin);
                 load_tile(a.W, a.n, i, k, Bt, nullptr, nullptr, false);
                 if (!diag) load_tile(a.W, a.n, j, k, Ct, nullptr, nullptr, false);
                 __syncthreads();
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
                 st_flag(fI(j, j), 1);
             }
         } else {
-            wait_flags(fL(j, j), nullptr, a.err);
+            wait_flags(fL(j, j), nullptr, a.err, a.max_spin);
             load_tile(a.Tout, a.n, j, j, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Ct, At, Bt, true, 1.0, 0.0);       // L_ij = A_ij Linv_jj^T
@@ -472,13 +476,13 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
         for (int e = threadIdx.x; e < TB * TS; e += blockDim.x) Ct[e] = 0.0;
         __syncthreads();
         for (int k = j; k < i; ++k) {
-            wait_flags(fL(i, k), fI(k, j), a.err);
+            wait_flags(fL(i, k), fI(k, j), a.err, a.max_spin);
             load_tile(a.W, a.n, i, k, At, nullptr, nullptr, false);
             load_tile(a.Tout, a.n, k, j, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Ct, At, Bt, false, 1.0, 1.0);       // acc += L_ik Linv_kj
         }
-        wait_flags(fI(i, i), nullptr, a.err);
+        wait_flags(fI(i, i), nullptr, a.err, a.max_spin);
         load_tile(a.Tout, a.n, i, i, At, nullptr, nullptr, false);
         __syncthreads();
         tile_gemm(Bt, At, Ct, false, -1.0, 0.0);          // Linv_ij = -Linv_ii acc
@@ -487,9 +491,9 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
     }
 }
 
-// T <- lower(T) * D^-1 (column scaling), upper triangle zeroed.  Block 0 also reports a timed-out
-// wait of the task graph through the shift counter (+1e6) and then clears the graph's counters for
-// the next call.
+// T <- lower(T) * D^-1 (column scaling), upper triangle zeroed.  Block 0 also counts a call of the
+// task graph in which a wait gave up (shifts[kWaitTimeoutSlot]) and then clears the graph's
+// counters for the next call.
 __global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, const double* dsc, int* counters,
                                                      int nctr, int* shifts, const int* run_if) {
     if (run_if && *run_if == 0) return;
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(256) void chol_epilogue(double* Tm, int64_t n, cons
         __shared__ int err;
         if (threadIdx.x == 0) err = counters[1];
         __syncthreads();
-        if (threadIdx.x == 0 && err) atomicAdd(shifts, 1000000);
+        if (threadIdx.x == 0 && err) atomicAdd(shifts + kWaitTimeoutSlot, 1);
         for (int e = threadIdx.x; e < nctr; e += blockDim.x) counters[e] = 0;
     }
     const int64_t total = n * n;
@@ -728,14 +732,15 @@ int64_t chol_counter_ints(int64_t n) {
 }
 
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
-                           double* dsc, int* shifts, hipStream_t s, const int* run_if) {
+                           double* dsc, int* shifts, hipStream_t s, const int* run_if, long long max_spin) {
     if (n <= 0) return hipSuccess;
+    if (max_spin <= 0) max_spin = kMaxSpin;
     const int T = (int)((n + TB - 1) / TB);
     // counters: [0] ticket, [1] error, then flagL (T*T), flagI (T*T); zero on entry, cleared again
     // by the epilogue
     const int nctr = (int)chol_counter_ints(n);
     CholArgs a{W, n, T, shift, scale, dsc, Tout, counters, counters + 2, counters + 2 + T * T, shifts, counters + 1,
-               run_if};
+               run_if, max_spin};
     hipLaunchKernelGGL(chol_graph, dim3((unsigned)(T * T - T + 1)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

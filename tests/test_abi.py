@@ -104,3 +104,30 @@ def test_server_without_gpu_and_null_arguments():
         assert lib.tucker_server_create(C.byref(o), C.byref(h)) == _lib.ERR_DEVICE
         assert not h.value
     assert lib.tucker_status_string(_lib.ERR_TIMEOUT).decode() == "timed out"
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a struct of include/tucker.h, compiled by the host C compiler."""
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{_lib.HEADER}"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    return vals[0], vals[1:]
+
+
+@pytest.mark.parametrize("cls,struct", [(_lib.Options, "tucker_options"), (_lib.Stats, "tucker_stats"),
+                                        (_lib.ServerOptions, "tucker_server_options"),
+                                        (_lib.Request, "tucker_request"), (_lib.ServedResult, "tucker_result"),
+                                        (_lib.ServerStats, "tucker_server_stats")])
+def test_binding_structs_match_the_header(cls, struct, tmp_path):
+    """The ctypes mirrors of the ABI structs have the C compiler's size and field offsets."""
+    names = [f for f, _ in cls._fields_]
+    size, offs = _c_layout(struct, names, tmp_path)
+    assert C.sizeof(cls) == size, struct
+    for name, off in zip(names, offs):
+        assert getattr(cls, name).offset == off, (struct, name)

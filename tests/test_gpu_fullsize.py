@@ -9,6 +9,11 @@ uses.  Their results are checked against:
   the core norm to 1e-5 (FP32) or 1e-3 (BF16 + FP32 refinement); the per-sweep fit (from
   ||X||^2 - ||G||^2 with the FP32 core) within the FP32 error of ||G||^2 amplified by the
   cancellation in that difference;
+* the FP64 oracle run live on the host for the 1080p stack (T-HOSVD + 20 sweeps, about 20 s, and one
+  more sweep for the precision variants): the reconstruction through the rotation-invariant
+  core-space difference, within 1e-5 plus the subspace-iteration allowance of tests/allowances.py
+  (FP32), or within 1e-3 plus one boundary direction pair per degenerate mode (BF16, FP16, FP8
+  after their FP32 refinement sweep); fit and core norm to 1e-5 (FP32) or 1e-3;
 * properties that hold at any size, evaluated on the host in FP64 from the GPU's own outputs:
   orthonormal factors, the identity fit = 1 - sqrt(||X||^2 - ||G||^2) / ||X|| for orthonormal
   factors (within the same cancellation bound), a fit history that never decreases by more than
@@ -23,6 +28,8 @@ import os
 import numpy as np
 import pytest
 
+import oracle
+from allowances import leading_containment, pair_allowance, si_allowance
 from synth import STACK_CONFIGS, make_stereo_stack
 
 pytestmark = pytest.mark.gpu
@@ -53,12 +60,12 @@ def _stack(name):
     return _CACHE[name]
 
 
-def _decompose(name, precision="fp32"):
+def _decompose(name, precision="fp32", **kw):
     import torch
     import paper_2104_04726_amd as tk
     c = STACK_CONFIGS[name]
     x32 = _stack(name)
-    ctx = tk.Context(0, precision=precision, refine_sweeps=1)
+    ctx = tk.Context(0, precision=precision, refine_sweeps=1, **kw)
     try:
         _say(f"decomposing {name} {precision}")
         res = ctx.decompose(torch.from_numpy(x32).cuda(), c["ranks"], c["sweeps"])
@@ -156,3 +163,66 @@ def test_exact_fit_history_with_tolerance_is_monotone():
         assert abs(h[-1] - h[-2]) < 1e-9
     g = _golden("stack1080")
     assert abs(res.fit - g["fits"][res.sweeps]) <= 1e-5
+
+
+# ------------------------------------------------------------------ live oracle at 1080p
+
+@pytest.fixture(scope="module")
+def oracle1080():
+    """The FP64 oracle on the 1080p stack: 20 sweeps (the FP32 run) and one more, resumed from
+    them (the reduced-precision runs end with an FP32 refinement sweep: 20 + 1)."""
+    import time
+    c = STACK_CONFIGS["stack1080"]
+    x = _stack("stack1080").astype(np.float64)
+    t = time.perf_counter()
+    _say("oracle: stack1080, T-HOSVD + 20 sweeps")
+    o20 = oracle.hooi(x, c["ranks"], 20)
+    _say(f"  {time.perf_counter() - t:.1f} s, fit {o20.fits[-1]:.10f}; one more sweep")
+    o21 = oracle.hooi(x, c["ranks"], 1, init=o20.factors)
+    _say(f"  fit {o21.fits[-1]:.10f}")
+    del x
+    return o20, o21
+
+
+def _as_dict(res, core, factors):
+    return dict(core=core, factors=factors, fit=res.fit)
+
+
+def test_fp32_1080_matches_live_oracle(oracle1080):
+    o, _ = oracle1080
+    c = STACK_CONFIGS["stack1080"]
+    x32, res, core, factors = _decompose("stack1080")
+    m = oracle.compare(_as_dict(res, core, factors), dict(core=o.core, factors=o.factors, fit=o.fits[-1]))
+    steps = 20 + c["sweeps"]          # cold-start steps + one warm step per sweep
+    recon_tol = 1e-5 + si_allowance(o.spectra, x32.shape, c["ranks"], steps)
+    _say(f"  fp32: fit {m['fit']:.2e} rho {m['rho']:.2e} core {m['core_norm']:.2e} recon {m['recon']:.2e} "
+         f"(bound {recon_tol:.2e}) sin {['%.2e' % v for v in m['sin_theta']]}")
+    assert m["fit"] <= 1e-5 and m["rho"] <= 1e-5 and m["core_norm"] <= 1e-5, m
+    assert m["recon"] <= recon_tol
+    for n in (0, 1):
+        k, sine, bound = leading_containment(o.factors[n], factors[n], o.spectra[n], steps)
+        _say(f"    mode {n + 1}: leading {k} directions contained to {sine:.2e} (bound {bound + 1e-5:.2e})")
+        assert k >= 1 and sine <= bound + 1e-5
+    assert m["sin_theta"][2] <= 1e-5                     # R3 = s3: the whole space
+    k, sine, bound = leading_containment(o.factors[3], factors[3], o.spectra[3], resid=0.0)
+    _say(f"    mode 4: leading {k} directions contained to {sine:.2e} (bound {bound + 1e-5:.2e})")
+    assert k >= 1 and sine <= bound + 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
+def test_lowp_1080_matches_live_oracle(oracle1080, prec):
+    """The precision variants: 20 sweeps with BF16 / FP16 / FP8 contractions, then one FP32
+    refinement sweep, against the oracle's 21 sweeps: reconstruction <= 1e-3 (plus one boundary
+    direction pair per degenerate mode), fit and core norm <= 1e-3."""
+    _, o = oracle1080
+    c = STACK_CONFIGS["stack1080"]
+    x32, res, core, factors = _decompose("stack1080", prec)
+    assert res.sweeps == c["sweeps"] and res.stats["refine_sweeps"] == 1
+    m = oracle.compare(_as_dict(res, core, factors), dict(core=o.core, factors=o.factors, fit=o.fits[-1]))
+    tol = 1e-3 + pair_allowance(o.spectra, c["ranks"])
+    _say(f"  {prec}: fit {m['fit']:.2e} core {m['core_norm']:.2e} recon {m['recon']:.2e} (bound {tol:.2e}) "
+         f"sin {['%.2e' % v for v in m['sin_theta']]}")
+    assert m["recon"] <= tol, m
+    assert m["fit"] <= 1e-3 and m["core_norm"] <= 1e-3, m
+    for u in factors:
+        assert np.linalg.norm(u.T @ u - np.eye(u.shape[1]), 2) <= 1e-5
