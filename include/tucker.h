@@ -259,6 +259,15 @@ tucker_status tucker_orthonormalize(tucker_ctx* ctx, const float* Z, int64_t row
 tucker_status tucker_gram_tn64(tucker_ctx* ctx, const float* Z, int64_t rows, int64_t cols, double* W);
 tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, double* T);
 
+/* tucker_chol_inv without any device allocation, for callers that cannot allocate (serving loops
+ * or harnesses that forbid hipMalloc).  Same arguments, result and errors as tucker_chol_inv, for
+ * n <= 512; larger n returns TUCKER_ERR_INVALID_ARG.  Its scratch (the working copy of W, the task
+ * graph's counters, the scaling) is a fixed array of about 2 MiB per GPU that the library holds
+ * until the process ends, shared by every call on that GPU: calls on one GPU that overlap in time
+ * (from several contexts, streams or threads) race and must be serialised by the caller.
+ * Synchronises the context's stream. */
+tucker_status tucker_chol_inv_noalloc(tucker_ctx* ctx, const double* W, int64_t n, double* T);
+
 /* Leading r eigenvectors (descending eigenvalues) of a symmetric n x n matrix, n <= 64,
  * by cyclic Jacobi in FP64.  S device n*n floats; U device n*r floats; lam device n doubles
  * (all eigenvalues, descending; nullable).  Stream-ordered. */

@@ -143,6 +143,7 @@ def _declare(lib):
     lib.tucker_orthonormalize.argtypes = [v, v, C.c_int64, C.c_int64, v]
     lib.tucker_gram_tn64.argtypes = [v, v, C.c_int64, C.c_int64, v]
     lib.tucker_chol_inv.argtypes = [v, v, C.c_int64, v]
+    lib.tucker_chol_inv_noalloc.argtypes = [v, v, C.c_int64, v]
     lib.tucker_sym_eig.argtypes = [v, v, C.c_int64, C.c_int64, v, v]
     lib.tucker_sumsq.argtypes = [v, v, C.c_int64, C.POINTER(C.c_double)]
     lib.tucker_status_string.argtypes = [C.c_int]
@@ -166,7 +167,7 @@ def _declare(lib):
     for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
                  "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
                  "tucker_quantize", "tucker_ttm_lowp", "tucker_gram_lowp",
-                 "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv",
+                 "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv", "tucker_chol_inv_noalloc",
                  "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):
         getattr(lib, name).restype = C.c_int
 

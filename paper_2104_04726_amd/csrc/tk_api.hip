@@ -19,6 +19,7 @@
 #include <atomic>
 #include <functional>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -39,6 +40,21 @@ hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* pa
                           hipStream_t s);
 hipError_t tk_diff_sumsq_f64(const double* A, const double* B, int64_t n, double* partial, int nblocks, double* out,
                              hipStream_t s);
+
+// ---- the allocation-free CholeskyQR half (tucker_chol_inv_noalloc): its scratch is one file-scope
+// device array per GPU.  In host code `scratch` names a host-side stand-in, never the device memory:
+// its device address is looked up once per device at context creation and kept in g_scratch.
+constexpr int64_t kNoAllocMaxN = 512;
+constexpr size_t kNoAllocAlign = 256;
+constexpr size_t align_up(size_t v) { return (v + kNoAllocAlign - 1) / kNoAllocAlign * kNoAllocAlign; }
+constexpr size_t kNoAllocW = 0;                                                     // n x n doubles
+constexpr size_t kNoAllocCtr = align_up(kNoAllocW + sizeof(double) * kNoAllocMaxN * kNoAllocMaxN);
+constexpr size_t kNoAllocCtrInts = 2 + 2 * ((kNoAllocMaxN + 63) / 64) * ((kNoAllocMaxN + 63) / 64);
+constexpr size_t kNoAllocDsc = align_up(kNoAllocCtr + sizeof(int) * kNoAllocCtrInts);     // n doubles
+constexpr size_t kNoAllocShifts = align_up(kNoAllocDsc + sizeof(double) * kNoAllocMaxN);  // 8 ints
+constexpr size_t kNoAllocBytes = align_up(kNoAllocShifts + 8 * sizeof(int));
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
 
 struct tucker_ctx {
     int device = 0;
@@ -1587,6 +1603,22 @@ void with_scratch(tucker_ctx* ctx, Fn layout) {
     layout(b);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Looks up this device's copy of `scratch` once (the device must be current).
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = static_cast<char*>(ptr);
+    return hipSuccess;
+}
+
 // After a step-level call that ran the Cholesky task graph: synchronise, record the pivot shifts and
 // timed-out waits (int counters as laid out by chol_inv_scaled) and fail when a wait gave up.
 void check_chol_calls(tucker_ctx* ctx, const int* shifts, hipStream_t s) {
@@ -1675,7 +1707,7 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
     }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess || noalloc_setup(o.device) != hipSuccess) {
         (void)hipGetLastError();
         tucker_destroy(c);
         return TUCKER_ERR_DEVICE;
@@ -2106,6 +2138,33 @@ tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, doubl
             dsc = a.take<double>(n);
             shifts = a.take<int>(8);
         });
+        TK_HIP(fill_zero(shifts, 8 * sizeof(int), ctx->stream));
+        TK_HIP(fill_zero(cw, chol_counter_ints(n) * (int64_t)sizeof(int), ctx->stream));
+        TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        TK_HIP(chol_inv_scaled(Wc, n, true, 0.0, T, cw, dsc, shifts, ctx->stream, nullptr,
+                               (long long)ctx->opt.wait_spin_limit));
+        check_chol_calls(ctx, shifts, ctx->stream);
+    });
+}
+
+tucker_status tucker_chol_inv_noalloc(tucker_ctx* ctx, const double* W, int64_t n, double* T) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!W || !T || n < 1) return TUCKER_ERR_INVALID_ARG;
+    if (n > kNoAllocMaxN) {
+        ctx->err = "tucker_chol_inv_noalloc: n = " + std::to_string(n) + " exceeds the scratch limit of " +
+                   std::to_string(kNoAllocMaxN);
+        return TUCKER_ERR_INVALID_ARG;
+    }
+    return guarded(ctx, [&]() {
+        char* base = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch[ctx->device] : nullptr;
+        if (!base) throw Fail{TUCKER_ERR_DEVICE, "scratch of this device was not set up"};
+        double* Wc = reinterpret_cast<double*>(base + kNoAllocW);
+        int* cw = reinterpret_cast<int*>(base + kNoAllocCtr);
+        double* dsc = reinterpret_cast<double*>(base + kNoAllocDsc);
+        int* shifts = reinterpret_cast<int*>(base + kNoAllocShifts);
+        // the counters of the task graph and the shift counters start at zero (a fill kernel, so that
+        // the enqueued work stays free of memset nodes)
         TK_HIP(fill_zero(shifts, 8 * sizeof(int), ctx->stream));
         TK_HIP(fill_zero(cw, chol_counter_ints(n) * (int64_t)sizeof(int), ctx->stream));
         TK_HIP(hipMemcpyAsync(Wc, W, n * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
