@@ -101,6 +101,11 @@ typedef struct {
                                     finishes normally and the call returns TUCKER_ERR_DEVICE.
                                     Tiny values exist to exercise that error path.            */
     tucker_start start;          /* initialisation of the factors (default TUCKER_START_THOSVD) */
+    int autotune;                /* 1: launch choices not yet fixed in this process (FP32 product
+                                    tile shape, FP64 Gram split count) are measured on the device
+                                    on first use and the fastest kept (tucker_autotune_dump);
+                                    0: such choices take the built-in heuristic.  Either way the
+                                    first call of a shape fixes its choice for the process.     */
 } tucker_options;
 
 /* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack
@@ -203,6 +208,31 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
 tucker_status tucker_reconstruct(tucker_ctx* ctx, const float* core, const float* const* factors,
                                  int ndim, const int64_t* dims, const int64_t* ranks, float* out);
 
+/* ---- Codec hand-off: ordered core and core quantisation ----
+ * The paper sets the bit rate of the representation by the rank of the core and its quantisation
+ * (Abstract; Sec. I).  These two calls prepare a decomposition for that. */
+
+/* All-orthogonal, energy-ordered core: for every mode, C_n = G_(n) G_(n)^T = V_n diag(sigma_n^2) V_n^T
+ * (eigenvalues descending, FP64 eigensolver), factors_out[n] = U_n V_n and
+ * core_out = G x_1 V_1^T ... x_N V_N^T.  The reconstruction (eq. (1)) is unchanged, the slices of
+ * core_out along every mode are mutually orthogonal with norms sigma_n, and keeping the leading k_n
+ * slices is then the rank-reduction knob (discarded energy sum_{i > k_n} sigma_n,i^2 per mode).
+ *   core, core_out  device, prod(ranks) floats (may not alias);
+ *   factors, factors_out  host arrays of ndim device pointers, dims[n] x ranks[n] floats each (may not alias);
+ *   sigma  device, nullable, sum(ranks) doubles: sigma_1 (ranks[0] values), then sigma_2, ...
+ * ranks[n] <= 1024 (TUCKER_ERR_UNSUPPORTED above).  Synchronises the stream when a rank exceeds 64. */
+tucker_status tucker_order_core(tucker_ctx* ctx, const float* core, const float* const* factors, int ndim,
+                                const int64_t* dims, const int64_t* ranks, float* core_out,
+                                float* const* factors_out, double* sigma);
+
+/* The leading keep[0] x ... x keep[N-1] block of a core (ranks) quantised uniformly with 2^(bits-1) - 1
+ * levels per sign: step = max|block| / (2^(bits-1) - 1), code = round-half-even(block / step) clamped,
+ * dequantized = code * step (each one correctly rounded binary32 operation).  codes (int32) and
+ * dequantized (float) are device arrays of prod(keep) entries; step is a host float (0 for an all-zero
+ * block).  2 <= bits <= 24, 1 <= keep[n] <= ranks[n].  Synchronises the stream. */
+tucker_status tucker_quantize_core(tucker_ctx* ctx, const float* core, int ndim, const int64_t* ranks,
+                                   const int64_t* keep, int bits, int32_t* codes, float* dequantized, float* step);
+
 /* ---- Step-level entry points (the building blocks of a sweep, exposed for testing) ---- */
 
 /* Mode-n product with a transposed factor (eq. (8)): out = in x_mode U^T.
@@ -268,9 +298,11 @@ tucker_status tucker_chol_inv(tucker_ctx* ctx, const double* W, int64_t n, doubl
  * Synchronises the context's stream. */
 tucker_status tucker_chol_inv_noalloc(tucker_ctx* ctx, const double* W, int64_t n, double* T);
 
-/* Leading r eigenvectors (descending eigenvalues) of a symmetric n x n matrix, n <= 64,
- * by cyclic Jacobi in FP64.  S device n*n floats; U device n*r floats; lam device n doubles
- * (all eigenvalues, descending; nullable).  Stream-ordered. */
+/* Leading r eigenvectors (descending eigenvalues) of a symmetric n x n matrix, n <= 1024, in FP64:
+ * cyclic Jacobi for n <= 64, two-sided block Jacobi (64 x 64 sub-problems solved exactly) above; the
+ * eigensolver behind the small-mode updates and the ordered core (the text after eq. (8)).
+ * S device n*n floats; U device n*r floats; lam device n doubles (all eigenvalues, descending;
+ * nullable).  Stream-ordered for n <= 64; above, it synchronises the stream once per sweep. */
 tucker_status tucker_sym_eig(tucker_ctx* ctx, const float* S, int64_t n, int64_t r,
                              float* U, double* lam);
 
@@ -303,6 +335,7 @@ typedef struct {
     int init_iters;
     uint64_t seed;
     int use_graphs;              /* 1: slots replay each request's sweep as a HIP graph       */
+    int autotune;                /* as in tucker_options (default 1)                          */
 } tucker_server_options;
 
 typedef struct {
@@ -353,6 +386,16 @@ tucker_status tucker_server_wait(tucker_server* srv, uint64_t id, double timeout
 tucker_status tucker_server_get_stats(tucker_server* srv, tucker_server_stats* out);
 /* Finishes the running requests, fails the queued ones, frees everything. */
 tucker_status tucker_server_destroy(tucker_server* srv);
+
+/* ---- Autotuner ----
+ * Launch choices (the output tile shape of the FP32 mode products, the split count of the FP64 Grams)
+ * are kept per (operation, shape, device) for the life of the process; see tucker_options.autotune.
+ * tucker_autotune_dump writes one line per choice ("op <id> dev <d> shape <5 numbers> choice <c> ms
+ * <time per candidate>", "(heuristic)" when nothing was timed) into buf (host, len bytes, always
+ * NUL-terminated when len > 0) and the full length including the NUL to *needed (nullable).
+ * tucker_autotune_clear forgets every choice (later calls choose again). */
+tucker_status tucker_autotune_dump(char* buf, size_t len, size_t* needed);
+tucker_status tucker_autotune_clear(void);
 
 /* ---- Diagnostics ---- */
 const char* tucker_status_string(tucker_status s);

@@ -84,7 +84,7 @@ class Context:
     def __init__(self, device: int = 0, stream=None, inner_iters: int = 1, init_iters: int = 20,
                  seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
                  refine_sweeps: int = 1, timing: bool = False, use_graphs: bool = False, inner_tol: float = 0.0,
-                 wait_spin_limit: int = 0, start: str = "thosvd"):
+                 wait_spin_limit: int = 0, start: str = "thosvd", autotune: bool = False):
         import torch
         lib = _lib.lib()
         opts = _lib.Options()
@@ -105,6 +105,7 @@ class Context:
         opts.inner_tol = float(inner_tol)
         opts.wait_spin_limit = int(wait_spin_limit)
         opts.start = {"thosvd": _lib.START_THOSVD, "sthosvd": _lib.START_STHOSVD}[start]
+        opts.autotune = 1 if autotune else 0
         self.device = int(device)
         self._h = C.c_void_p()
         _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))
@@ -168,6 +169,38 @@ class Context:
         _check(_lib.lib().tucker_reconstruct(self._h, C.c_void_p(core.data_ptr()), fptrs, len(dims),
                                              _lib.i64(dims), _lib.i64(ranks), C.c_void_p(out.data_ptr())), self._h)
         return out
+
+    # ---------------------------------------------------------------- codec hand-off
+    def order_core(self, core, factors):
+        """All-orthogonal, energy-ordered core: returns (core, factors, sigma list per mode)."""
+        import torch
+        core = _f32_device(core, "core")
+        factors = [_f32_device(u, "factor") for u in factors]
+        dims = [int(u.shape[0]) for u in factors]
+        ranks = list(core.shape)
+        out = torch.empty_like(core)
+        fout = [torch.empty_like(u) for u in factors]
+        sig = torch.empty(sum(ranks), dtype=torch.float64, device=core.device)
+        fin = (C.c_void_p * len(factors))(*[u.data_ptr() for u in factors])
+        fo = (C.c_void_p * len(factors))(*[u.data_ptr() for u in fout])
+        _check(_lib.lib().tucker_order_core(self._h, C.c_void_p(core.data_ptr()), fin, len(dims), _lib.i64(dims),
+                                            _lib.i64(ranks), C.c_void_p(out.data_ptr()), fo,
+                                            C.c_void_p(sig.data_ptr())), self._h)
+        return out, fout, list(torch.split(sig, ranks))
+
+    def quantize_core(self, core, keep, bits: int):
+        """Leading block `keep` of the core, uniformly quantised: returns (codes int32, dequantised, step)."""
+        import torch
+        core = _f32_device(core, "core")
+        ranks = list(core.shape)
+        keep = [int(k) for k in keep]
+        codes = torch.empty(keep, dtype=torch.int32, device=core.device)
+        deq = torch.empty(keep, dtype=torch.float32, device=core.device)
+        step = C.c_float(0.0)
+        _check(_lib.lib().tucker_quantize_core(self._h, C.c_void_p(core.data_ptr()), len(ranks), _lib.i64(ranks),
+                                               _lib.i64(keep), int(bits), C.c_void_p(codes.data_ptr()),
+                                               C.c_void_p(deq.data_ptr()), C.byref(step)), self._h)
+        return codes, deq, float(step.value)
 
     # ---------------------------------------------------------------- building blocks
     def ttm(self, x, mode: int, U):
@@ -283,6 +316,19 @@ class Context:
         return out
 
 
+def autotune_table() -> str:
+    """The autotuner's choices so far in this process, one line per (operation, shape, device)."""
+    need = C.c_size_t(0)
+    _lib.lib().tucker_autotune_dump(None, 0, C.byref(need))
+    buf = C.create_string_buffer(int(need.value) + 1)
+    _lib.lib().tucker_autotune_dump(buf, len(buf), C.byref(need))
+    return buf.value.decode()
+
+
+def autotune_clear() -> None:
+    _lib.lib().tucker_autotune_clear()
+
+
 _default = {}
 
 
@@ -348,12 +394,13 @@ class Server:
     tensor must stay alive until wait() returns its result."""
 
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0, inner_iters: int = 1,
-                 init_iters: int = 20, seed: int = 0x5EED, use_graphs: bool = True):
+                 init_iters: int = 20, seed: int = 0x5EED, use_graphs: bool = True, autotune: bool = True):
         o = _lib.ServerOptions()
         _lib.lib().tucker_default_server_options(C.byref(o))
         o.device, o.slots, o.hbm_budget_bytes = int(device), int(slots), int(hbm_budget_bytes)
         o.inner_iters, o.init_iters, o.seed = int(inner_iters), int(init_iters), int(seed)
         o.use_graphs = 1 if use_graphs else 0
+        o.autotune = 1 if autotune else 0
         h = C.c_void_p()
         _check(_lib.lib().tucker_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -34,6 +34,7 @@ class Options(C.Structure):
         ("timing", C.c_int),
         ("wait_spin_limit", C.c_int64),
         ("start", C.c_int),
+        ("autotune", C.c_int),
     ]
 
 
@@ -69,6 +70,7 @@ class ServerOptions(C.Structure):
         ("init_iters", C.c_int),
         ("seed", C.c_uint64),
         ("use_graphs", C.c_int),
+        ("autotune", C.c_int),
     ]
 
 
@@ -139,6 +141,8 @@ def _declare(lib):
                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.tucker_reconstruct.argtypes = [v, v, FPP, C.c_int, I64P, I64P, v]
     lib.tucker_ttm.argtypes = [v, v, C.c_int, I64P, C.c_int, v, C.c_int64, v]
+    lib.tucker_order_core.argtypes = [v, v, FPP, C.c_int, I64P, I64P, v, FPP, v]
+    lib.tucker_quantize_core.argtypes = [v, v, C.c_int, I64P, I64P, C.c_int, v, v, C.POINTER(C.c_float)]
     lib.tucker_gram.argtypes = [v, v, C.c_int, I64P, C.c_int, v]
     lib.tucker_orthonormalize.argtypes = [v, v, C.c_int64, C.c_int64, v]
     lib.tucker_gram_tn64.argtypes = [v, v, C.c_int64, C.c_int64, v]
@@ -146,6 +150,10 @@ def _declare(lib):
     lib.tucker_chol_inv_noalloc.argtypes = [v, v, C.c_int64, v]
     lib.tucker_sym_eig.argtypes = [v, v, C.c_int64, C.c_int64, v, v]
     lib.tucker_sumsq.argtypes = [v, v, C.c_int64, C.POINTER(C.c_double)]
+    lib.tucker_autotune_dump.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.tucker_autotune_dump.restype = C.c_int
+    lib.tucker_autotune_clear.argtypes = []
+    lib.tucker_autotune_clear.restype = C.c_int
     lib.tucker_status_string.argtypes = [C.c_int]
     lib.tucker_status_string.restype = C.c_char_p
     lib.tucker_last_error.argtypes = [v]
@@ -166,6 +174,7 @@ def _declare(lib):
         getattr(lib, name).restype = C.c_int
     for name in ("tucker_validate", "tucker_workspace_size", "tucker_create", "tucker_destroy", "tucker_decompose",
                  "tucker_decompose_ex", "tucker_reconstruct", "tucker_ttm", "tucker_gram",
+                 "tucker_order_core", "tucker_quantize_core",
                  "tucker_quantize", "tucker_ttm_lowp", "tucker_gram_lowp",
                  "tucker_orthonormalize", "tucker_gram_tn64", "tucker_chol_inv", "tucker_chol_inv_noalloc",
                  "tucker_sym_eig", "tucker_sumsq", "tucker_get_stats"):

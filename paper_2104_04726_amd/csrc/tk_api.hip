@@ -130,6 +130,7 @@ struct Plan {
     int64_t Pf_elems = 0;
 
     float* U32[TUCKER_MAX_ORDER]{};
+    bool ident[TUCKER_MAX_ORDER]{};     // U_n is exactly the identity (a full-rank mode started from it)
     double* Vsm[TUCKER_MAX_ORDER]{};    // small modes: the whole eigenvector basis of the last update
     bool vsm_valid[TUCKER_MAX_ORDER]{};
     double* U64[TUCKER_MAX_ORDER]{};
@@ -535,14 +536,37 @@ void gram(Run& r, const float* in, const int64_t* dims, int N, int n, int stage 
         oa = MK;
         ob = MK;
     }
-    const int splits = gram_splits(s, g.K);
-    int64_t ks = (g.K + splits - 1) / splits;
-    ks = (ks + 15) / 16 * 16;
-    g.k_split = ks;
-    const int nsplit = (int)((g.K + ks - 1) / ks);
-    if ((int64_t)nsplit * s * s > p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer too small"};
+    // split count: the occupancy heuristic, or the autotuner's pick among it, half and double of it
+    // (each one fixed reduction order) within the capacity of the partial buffer
+    const int h = gram_splits(s, g.K);
+    std::vector<int> cand{h};
+    for (int c : {std::max(1, h / 2), 2 * h, std::max(1, h / 4)}) {
+        int64_t ks = ((g.K + c - 1) / c + 15) / 16 * 16;
+        const int64_t ns = (g.K + ks - 1) / ks;
+        if (ns * s * s <= p.P_elems && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
+    auto plan_split = [&](int splits, int64_t& ks) {
+        ks = ((g.K + splits - 1) / splits + 15) / 16 * 16;
+        return (int)((g.K + ks - 1) / ks);
+    };
     g.c = plain(p.P, s);
     g.c_zstride = s * s;
+    auto launch = [&](int c) {
+        GemmArgs gc = g;
+        int64_t ks = 0;
+        const int nsplit = plan_split(cand[c], ks);
+        gc.k_split = ks;
+        hipError_t e = gemm_f64(gc, oa, ob, EPI_STORE, true, true, r.st);
+        return e != hipSuccess ? e : gram_reduce64(p.P, nsplit, s, s * s, p.S64, r.st);
+    };
+    const int64_t shape[5] = {s, g.K, A, B, p.P_elems / (s * s)};
+    hipError_t te = hipSuccess;
+    const int choice = tune_choose(kTuneGramSplit, shape, (int)cand.size(), 0, r.st, launch, &te);
+    TK_HIP(te);
+    int64_t ks = 0;
+    const int nsplit = plan_split(cand[std::min<int>(choice, (int)cand.size() - 1)], ks);
+    if ((int64_t)nsplit * s * s > p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Gram partial buffer too small"};
+    g.k_split = ks;
     {
         StageTimer t(r, stage);
         TK_HIP(gemm_f64(g, oa, ob, EPI_STORE, true, true, r.st));
@@ -905,6 +929,7 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
 void identity_factor(Run& r, int n) {
     TK_HIP(fill_identity_f32(r.p.U32[n], r.p.s[n], r.p.R[n], r.st));
     TK_HIP(fill_identity_f64(r.p.U64[n], r.p.s[n], r.p.R[n], r.st));
+    r.p.ident[n] = r.p.s[n] == r.p.R[n];
 }
 
 // G = X x_1 U1^T ... x_N UN^T into p.G
@@ -1059,7 +1084,8 @@ void sweep_tree(Run& r) {
     // T34 = X x_3 U3^T x_4 U4^T (full-tensor pass, memory-bound)
     {
         StageTimer t(r, TUCKER_STAGE_PASS_A);
-        TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.T34, r.st));
+        TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.T34, r.st,
+                        p.ident[2]));
     }
     // mode 1: Y0 = T34 x_2 U2^T, S0 = Y0_(1) Y0_(1)^T
     if (p.kind[0] != FIXED) {
@@ -1089,7 +1115,7 @@ void sweep_tree(Run& r) {
         {
             StageTimer t(r, TUCKER_STAGE_TTM_Y2);
             TK_HIP(pair_ttm(p.T1, R0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.Y1,
-                            r.st));
+                            r.st, p.ident[2]));
         }
         if (direct_update_ok(r, 1) && p.kind[0] != FIXED) {
             // Y1^T U2 = T34 x_1 U1^T x_2 U2^T = Y0 x_1 U1^T: contracted over s1 from Y0 (still resident
@@ -1127,7 +1153,8 @@ void sweep_tree(Run& r) {
     }
     // core G = T12 x_3 U3^T x_4 U4^T
     StageTimer t(r, TUCKER_STAGE_CORE);
-    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
+    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st,
+                    p.ident[2]));
 }
 
 // ------------------------------------------------------------------ reduced-precision sweep
@@ -1211,7 +1238,8 @@ void sweep_tree_lp(Run& r) {
     {
         StageTimer t(r, TUCKER_STAGE_PASS_A);
         TK_HIP(pair_lowp(p.Xlp, s0 * s1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, p.prec,
-                         p.prec == TUCKER_FP8_E4M3 ? p.xscale : nullptr, ip, (int)R23p, p.T34lp, r.st));
+                         p.prec == TUCKER_FP8_E4M3 ? p.xscale : nullptr, ip, (int)R23p, p.T34lp, r.st,
+                         p.kind[2] == FIXED && p.ident[2]));
     }
     // mode 1: Y0 = T34 x_2 U2^T (k = w; n = (h, j)), S0 = Y0_(1) Y0_(1)^T
     {
@@ -1268,7 +1296,8 @@ void sweep_tree_lp(Run& r) {
         }
     }
     StageTimer t(r, TUCKER_STAGE_CORE);
-    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st));
+    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st,
+                    p.ident[2]));
 }
 
 void sweep_generic(Run& r) {
@@ -1759,6 +1788,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         }
     }
     return guarded(ctx, [&]() {
+        TuneScope tune(ctx->opt.autotune != 0);
         Run r{ctx, Plan{}, ctx->stream, tensor};
         Plan& p = r.p;
         ctx->stats = tucker_stats{};
@@ -1940,12 +1970,124 @@ tucker_status tucker_reconstruct(tucker_ctx* ctx, const float* core, const float
     for (int n = 0; n < ndim; ++n)
         if (!factors[n]) return TUCKER_ERR_INVALID_ARG;
     return guarded(ctx, [&]() {
+        TuneScope tune(ctx->opt.autotune != 0);
         Run r{ctx, Plan{}, ctx->stream, nullptr};
         make_plan(r.p, ndim, dims, ranks, 0);
         bind(ctx, r.p);
         float* U[TUCKER_MAX_ORDER];
         for (int n = 0; n < ndim; ++n) U[n] = const_cast<float*>(factors[n]);
         expand_chain(r, core, U, out, nullptr);
+    });
+}
+
+tucker_status tucker_order_core(tucker_ctx* ctx, const float* core, const float* const* factors, int ndim,
+                                const int64_t* dims, const int64_t* ranks, float* core_out, float* const* factors_out,
+                                double* sigma) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    ctx->err.clear();
+    std::string why;
+    tucker_status st = validate_args(ndim, dims, ranks, 0, 0.0, why);
+    if (st != TUCKER_OK) {
+        ctx->err = why;
+        return st;
+    }
+    if (!core || !factors || !core_out || !factors_out) return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n) {
+        if (!factors[n] || !factors_out[n]) return TUCKER_ERR_INVALID_ARG;
+        if (ranks[n] > 1024) {
+            ctx->err = "tucker_order_core: ranks above 1024 are not supported";
+            return TUCKER_ERR_UNSUPPORTED;
+        }
+    }
+    return guarded(ctx, [&]() {
+        Run r{ctx, Plan{}, ctx->stream, nullptr};
+        Plan& p = r.p;
+        const int N = ndim;
+        const int64_t G = prod(ranks, 0, N);
+        int64_t rmax = 1, rsum = 0, work = 1, pmax = 1;
+        for (int n = 0; n < N; ++n) {
+            rmax = std::max(rmax, ranks[n]);
+            rsum += ranks[n];
+            if (ranks[n] > kSmallMode) {
+                work = std::max<int64_t>(work, sym_eig_work_doubles((int)ranks[n]));
+                pmax = std::max<int64_t>(pmax, (int64_t)gram_splits(ranks[n], G / ranks[n]) * ranks[n] * ranks[n]);
+            }
+        }
+        double *V64 = nullptr, *lam = nullptr, *ework = nullptr;
+        float *V32 = nullptr, *buf0 = nullptr, *buf1 = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            p.Fpart = a.take<double>(64 * 64 * 64);
+            p.S64_elems = rmax * rmax;
+            p.S64 = a.take<double>(p.S64_elems);
+            p.P_elems = pmax;
+            p.P = a.take<double>(pmax);
+            V64 = a.take<double>(rmax * rmax * N);
+            V32 = a.take<float>(rmax * rmax * N);
+            lam = a.take<double>(rsum);
+            ework = a.take<double>(work);
+            buf0 = a.take<float>(G);
+            buf1 = a.take<float>(G);
+        });
+        // the rotation of every mode comes from the original core: rotating mode m leaves the Gram of
+        // every other mode unchanged (it multiplies that unfolding by an orthogonal matrix on the right)
+        int64_t loff = 0;
+        for (int n = 0; n < N; ++n) {
+            const int64_t R = ranks[n];
+            gram(r, core, ranks, N, n);
+            double* Vn = V64 + rmax * rmax * n;
+            float* Vn32 = V32 + rmax * rmax * n;
+            if (R <= kSmallMode) {
+                TK_HIP(jacobi_eig(p.S64, (int)R, (int)R, Vn, Vn32, lam + loff, r.st));
+            } else {
+                TK_HIP(sym_eig_blocked(p.S64, (int)R, (int)R, lam + loff, Vn, Vn32, ework, r.st));
+            }
+            // U_n V_n: FP32 factor times the FP64 rotation, FP64 accumulation, rounded once
+            GemmArgs g{};
+            g.alpha = 1.0;
+            g.M = dims[n];
+            g.N = R;
+            g.K = R;
+            g.a = plain(factors[n], R);     // A(m, k) = U[m][k]
+            g.b = plain(Vn, R);             // B(k, n) = V[k][n]
+            g.c = plain(factors_out[n], R);
+            g.c_f32 = 1;
+            TK_HIP(gemm_f64(g, MK, KM, EPI_STORE, true, false, r.st));
+            loff += R;
+        }
+        if (sigma) TK_HIP(sqrt_clamp(lam, rsum, sigma, r.st));
+        // G <- G x_1 V_1^T ... x_N V_N^T
+        int64_t d[TUCKER_MAX_ORDER];
+        for (int n = 0; n < N; ++n) d[n] = ranks[n];
+        const float* cur = core;
+        float* bufs[2] = {buf0, buf1};
+        for (int n = 0; n < N; ++n) {
+            float* dst = (n == N - 1) ? core_out : bufs[n & 1];
+            ttm(r, cur, d, N, n, V32 + rmax * rmax * n, ranks[n], false, dst);
+            cur = dst;
+        }
+    });
+}
+
+tucker_status tucker_quantize_core(tucker_ctx* ctx, const float* core, int ndim, const int64_t* ranks,
+                                   const int64_t* keep, int bits, int32_t* codes, float* dequantized, float* step) {
+    if (!ctx) return TUCKER_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!core || !ranks || !keep || !codes || !dequantized || !step || ndim < 1 || ndim > TUCKER_MAX_ORDER ||
+        bits < 2 || bits > 24)
+        return TUCKER_ERR_INVALID_ARG;
+    for (int n = 0; n < ndim; ++n)
+        if (ranks[n] < 1 || keep[n] < 1 || keep[n] > ranks[n]) return TUCKER_ERR_INVALID_ARG;
+    return guarded(ctx, [&]() {
+        const int64_t total = prod(keep, 0, ndim);
+        float *blk = nullptr, *scal = nullptr;
+        with_scratch(ctx, [&](Arena& a) {
+            blk = a.take<float>(total);
+            scal = a.take<float>(2);
+        });
+        TK_HIP(gather_block(core, ndim, ranks, keep, blk, ctx->stream));
+        TK_HIP(quantize_uniform(blk, total, bits, scal, codes, dequantized, scal + 1, ctx->stream));
+        TK_HIP(hipMemcpyAsync(step, scal + 1, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        TK_HIP(hipStreamSynchronize(ctx->stream));
     });
 }
 
@@ -2176,15 +2318,21 @@ tucker_status tucker_chol_inv_noalloc(tucker_ctx* ctx, const double* W, int64_t 
 
 tucker_status tucker_sym_eig(tucker_ctx* ctx, const float* S, int64_t n, int64_t rr, float* U, double* lam) {
     if (!ctx) return TUCKER_ERR_INVALID_ARG;
-    if (!S || !U || n < 1 || n > 64 || rr < 1 || rr > n) return TUCKER_ERR_INVALID_ARG;
+    if (!S || !U || n < 1 || n > 1024 || rr < 1 || rr > n) return TUCKER_ERR_INVALID_ARG;
     return guarded(ctx, [&]() {
-        double *S64 = nullptr, *U64 = nullptr;
+        double *S64 = nullptr, *U64 = nullptr, *work = nullptr;
         with_scratch(ctx, [&](Arena& a) {
             S64 = a.take<double>(n * n);
             U64 = a.take<double>(n * rr);
+            if (n > kSmallMode) work = a.take<double>(sym_eig_work_doubles((int)n));
         });
         TK_HIP(f32_to_f64(S, S64, n * n, ctx->stream));
-        TK_HIP(jacobi_eig(S64, (int)n, (int)rr, U64, U, lam, ctx->stream));
+        if (n <= kSmallMode) {
+            TK_HIP(jacobi_eig(S64, (int)n, (int)rr, U64, U, lam, ctx->stream));
+        } else {
+            int sweeps = 0;
+            TK_HIP(sym_eig_blocked(S64, (int)n, (int)rr, lam, nullptr, U, work, ctx->stream, &sweeps));
+        }
     });
 }
 
@@ -2201,6 +2349,22 @@ tucker_status tucker_sumsq(tucker_ctx* ctx, const float* x, int64_t n, double* r
         TK_HIP(hipMemcpyAsync(result, out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         TK_HIP(hipStreamSynchronize(ctx->stream));
     });
+}
+
+tucker_status tucker_autotune_dump(char* buf, size_t len, size_t* needed) {
+    const std::string t = tune_dump();
+    if (needed) *needed = t.size() + 1;
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, t.size());
+        std::memcpy(buf, t.data(), n);
+        buf[n] = '\0';
+    }
+    return TUCKER_OK;
+}
+
+tucker_status tucker_autotune_clear(void) {
+    tune_clear();
+    return TUCKER_OK;
 }
 
 const char* tucker_status_string(tucker_status s) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
+#include <string>
 
 namespace tk {
 
@@ -83,8 +85,9 @@ hipError_t small_ttm(const float* in, int64_t A, int64_t K, int64_t B, const flo
 //   expand == false: out[a][r][t] = sum_{c,i} U3[c*R3+r] U4[i*R4+t] in[a][c][i]
 //   expand == true : out[a][c][i] = sum_{r,t} U3[c*R3+r] U4[i*R4+t] in[a][r][t]
 //   (U3 is p x R3, U4 is q x R4 in both cases)
+//   u3_identity: U3 is the p x p identity (a mode kept at full rank); its product is skipped
 hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, int R3,
-                    const float* U4, int R4, bool expand, float* out, hipStream_t s);
+                    const float* U4, int R4, bool expand, float* out, hipStream_t s, bool u3_identity = false);
 bool pair_ttm_supported(int p, int q);
 
 // Fibre Gram of a (A, L) row-major matrix (L <= 64): F = sum_a x_a x_a^T (fp64, L x L),
@@ -149,6 +152,51 @@ int orth_check_partials();
 // *need != 0: U32 = (float)U64; else U64 = Q1 and U32 = (float)Q1 (n values)
 hipError_t finish_factor(const int* need, const double* Q1, double* U64, float* U32, int64_t n, hipStream_t s);
 int64_t chol_counter_ints(int64_t n);
+
+// Eigen-decomposition of a symmetric n x n FP64 matrix A (row-major, read-only), n <= 1024, by two-sided
+// block Jacobi (tk_eig.hip): all eigenvalues descending to lam (nullable, n doubles), the eigenvectors
+// of the r largest to U (nullable, n x r FP64) and U32 (nullable, FP32).  work: sym_eig_work_doubles(n)
+// doubles of scratch.  Synchronises the stream once per sweep (convergence test); *sweeps_out (nullable)
+// receives the sweep count.
+int64_t sym_eig_work_doubles(int n);
+hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U, float* U32, double* work,
+                           hipStream_t s, int* sweeps_out = nullptr);
+
+// ---------------------------------------------------------------------------------------
+// Autotuner (tk_tune.hip): measured launch choices cached per (operation, shape, device)
+// ---------------------------------------------------------------------------------------
+enum TuneOp { kTuneF32Tile = 1, kTuneGramSplit = 2 };
+void tune_set_enabled(bool on);     // this thread's calls may time new keys
+bool tune_enabled();
+// The cached choice for (op, device, shape), else, when tuning is enabled and the stream is not
+// capturing, candidates 0..ncand-1 launched (twice each, the second timed) and the fastest cached;
+// otherwise `heuristic`.  launch(c) enqueues candidate c on s.
+int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStream_t s,
+                const std::function<hipError_t(int)>& launch, hipError_t* err);
+std::string tune_dump();
+void tune_clear();
+size_t tune_size();
+// RAII: tuning on for this thread while in scope (restores the previous state)
+struct TuneScope {
+    bool prev;
+    explicit TuneScope(bool on) : prev(tune_enabled()) { tune_set_enabled(on); }
+    ~TuneScope() { tune_set_enabled(prev); }
+};
+
+// ---------------------------------------------------------------------------------------
+// Codec hand-off (tk_codec.hip)
+// ---------------------------------------------------------------------------------------
+struct DimPack {
+    int64_t v[8];
+};
+// out (prod keep) = the leading keep[0] x ... x keep[N-1] block of in (dims), row-major
+hipError_t gather_block(const float* in, int N, const int64_t* dims, const int64_t* keep, float* out, hipStream_t s);
+// uniform mid-tread quantiser of n floats with 2^(bits-1) - 1 levels per sign: codes, dequantised
+// values and the step (device float); amax_scratch: one device float
+hipError_t quantize_uniform(const float* x, int64_t n, int bits, float* amax_scratch, int32_t* codes, float* deq,
+                            float* step, hipStream_t s);
+// out[i] = sqrt(max(lam[i], 0))
+hipError_t sqrt_clamp(const double* lam, int64_t n, double* out, hipStream_t s);
 
 // Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading
 // r eigenvectors (descending) to U64 (n x r fp64) and U32 (n x r fp32, nullable), all

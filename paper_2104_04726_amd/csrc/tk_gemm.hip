@@ -706,8 +706,18 @@ hipError_t gemm_f32(const GemmArgs& gin, Orient oa, Orient ob, Epilogue epi, boo
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (epi == EPI_STORE) {
         if (acc64) return by_orient<float, float, float, EPI_STORE, true, 128, 128, TK_F32_BK>(g, oa, ob, s);
-        if (narrow_tiles_pay(g)) return by_orient<float, float, float, EPI_STORE, false, 128, 64, TK_F32_BK>(g, oa, ob, s);
-        return by_orient<float, float, float, EPI_STORE, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
+        // output tile 128 x 128 (0) or 128 x 64 (1): the same sums in the same order either way, so the
+        // choice is left to the autotuner (the load-balance heuristic without it)
+        auto launch = [&](int c) {
+            return c == 1 ? by_orient<float, float, float, EPI_STORE, false, 128, 64, TK_F32_BK>(g, oa, ob, s)
+                          : by_orient<float, float, float, EPI_STORE, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
+        };
+        const int64_t shape[5] = {g.M, g.N, g.K, g.k_split,
+                                  (int64_t)oa * 4 + (int64_t)ob * 2 + (g.b.seg < (int64_t(1) << 61) ? 1 : 0)};
+        hipError_t e = hipSuccess;
+        const int c = tune_choose(kTuneF32Tile, shape, 2, narrow_tiles_pay(g) ? 1 : 0, s, launch, &e);
+        if (e != hipSuccess) return e;
+        return launch(c);
     }
     if (epi == EPI_ADD) return by_orient<float, float, float, EPI_ADD, false, 128, 128, TK_F32_BK>(g, oa, ob, s);
     return by_orient<float, float, float, EPI_RESID, false, 128, 128, TK_F32_BK>(g, oa, ob, s);

@@ -37,8 +37,10 @@ hipError_t slice_scales(const float* x, int64_t A, int L, float* partial, int nb
 hipError_t factor_lowp(const float* U, int64_t rows, int64_t R, int64_t ldk, int prec, float* scale, void* Ut,
                        hipStream_t s);
 // out[a][r R4 + t] = sum_{c,i} U3[c][r] U4[i][t] dec(in[a][c q + i]) scale[c q + i], rows of ldo
-// 16-bit outp elements, the tail of each row zero
+// 16-bit outp elements, the tail of each row zero.  u3_identity: U3 is the p x p identity (a mode
+// kept at full rank), which lets the fixed-shape kernels skip its product.
 hipError_t pair_lowp(const void* in, int64_t A, int p, int q, const float* U3, int R3, const float* U4, int R4,
-                     int prec, const float* scale, int outp, int ldo, void* out, hipStream_t s);
+                     int prec, const float* scale, int outp, int ldo, void* out, hipStream_t s,
+                     bool u3_identity = false);
 
 }  // namespace tk

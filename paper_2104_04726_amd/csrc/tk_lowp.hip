@@ -64,14 +64,9 @@ __device__ __forceinline__ uint8_t enc_e4m3(float x) {
     const int E = e + 7;                                  // 1..15 here (a < 464)
     return sign | (uint8_t)(E << 3) | (uint8_t)m3;
 }
-__device__ __forceinline__ float dec_e4m3(uint8_t b) {
-    const int E = (b >> 3) & 15, m = b & 7;
-    float v;
-    if (E == 15 && m == 7) v = __uint_as_float(0x7fc00000u);
-    else if (E == 0) v = (float)m * 0.001953125f;          // m * 2^-9
-    else v = ldexpf(1.0f + (float)m * 0.125f, E - 7);
-    return (b & 0x80) ? -v : v;
-}
+// decode by the hardware conversion (v_cvt_f32_fp8), which reads gfx950's FP8 bytes as OCP E4M3 like
+// the matrix instructions do; exact (every E4M3 value is a binary32 value)
+__device__ __forceinline__ float dec_e4m3(uint8_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
 
 template <int P> struct Codec;
 template <> struct Codec<LP_BF16> {
@@ -429,9 +424,11 @@ __global__ __launch_bounds__(256) void from_lp_kernel(const typename Codec<P>::S
 // ---------------------------------------------------------------------------- two-mode pass
 // Fixed-shape version of the pass below (P x Q fibres, ranks R3, R4, output rows of LDO): the
 // chunk of 256 fibres is read with 16-byte coalesced loads prefetched one chunk ahead, decoded
-// into LDS, mapped one fibre per thread with U3 in registers and U4 in LDS, and written back
-// with 16-byte stores.
-template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO>
+// into LDS, mapped one fibre per thread with U3 in registers and U4 in LDS, and written back with
+// 16-byte stores.  ID3: U3 is the identity (a mode kept at full rank), so its product is skipped.  Only FP8
+// carries slice scales.  The decode walks each 16-byte vector's elements with one division per
+// vector (fibre and position advance by increments).
+template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO, bool ID3>
 __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S* __restrict__ in, int64_t A,
                                                      const float* __restrict__ U3, const float* __restrict__ U4,
                                                      const float* __restrict__ scale, uint16_t* __restrict__ out) {
@@ -443,16 +440,20 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
     constexpr int NV_IN = FPB * LIN / EPV;              // vectors per full chunk
     constexpr int VPT = (NV_IN + 255) / 256;
     constexpr int NV_OUT = FPB * LDO * 2 / 16;
+    constexpr bool SCALED = (P == LP_FP8);
     static_assert((FPB * LIN) % EPV == 0 && (FPB * LDO * 2) % 16 == 0, "chunk not a whole number of vectors");
+    static_assert(!ID3 || PP == R3, "an identity U3 keeps the mode's size");
+    static_assert(EPV <= LIN, "a vector spans at most two fibres");
     __shared__ float fin[FPB * SIN];
     __shared__ __attribute__((aligned(16))) uint16_t fout[FPB * LDO];
-    __shared__ float u4s[QQ * R4];
     __shared__ float sc[LIN];
-    for (int i = threadIdx.x; i < QQ * R4; i += 256) u4s[i] = U4[i];
-    for (int i = threadIdx.x; i < LIN; i += 256) sc[i] = scale ? scale[i] : 1.0f;
+    __shared__ float u4[QQ * R4];
+    if (SCALED)
+        for (int i = threadIdx.x; i < LIN; i += 256) sc[i] = scale ? scale[i] : 1.0f;
+    for (int i = threadIdx.x; i < QQ * R4; i += 256) u4[i] = U4[i];
     float u3[PP * R3];
 #pragma unroll
-    for (int i = 0; i < PP * R3; ++i) u3[i] = U3[i];
+    for (int i = 0; i < PP * R3; ++i) u3[i] = ID3 ? 0.f : U3[i];
 
     const int64_t nchunks = (A + FPB - 1) / FPB;
     const int64_t full = A / FPB;
@@ -479,11 +480,19 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
                 const int i = threadIdx.x + 256 * u;
                 if (i < NV_IN) {
                     const S* e = (const S*)&pre[u];
+                    const int g0 = EPV * i;
+                    const int fb = g0 / LIN;
+                    int l = g0 - fb * LIN;
+                    float* dst = fin + fb * SIN;
 #pragma unroll
                     for (int j = 0; j < EPV; ++j) {
-                        const int g = EPV * i + j;
-                        const int l = g % LIN;
-                        fin[(g / LIN) * SIN + l] = Codec<P>::dec(e[j]) * sc[l];
+                        const float v = Codec<P>::dec(e[j]);
+                        dst[l] = SCALED ? v * sc[l] : v;
+                        ++l;
+                        if (l == LIN) {
+                            l = 0;
+                            dst += SIN;
+                        }
                     }
                 }
             }
@@ -491,7 +500,8 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
             const S* src = in + f0 * LIN;
             for (int g = threadIdx.x; g < nf * LIN; g += 256) {
                 const int l = g % LIN;
-                fin[(g / LIN) * SIN + l] = Codec<P>::dec(src[g]) * sc[l];
+                const float v = Codec<P>::dec(src[g]);
+                fin[(g / LIN) * SIN + l] = SCALED ? v * sc[l] : v;
             }
         }
         __syncthreads();
@@ -511,7 +521,7 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
                 for (int c = 0; c < PP; ++c) xc[c] = x[c * QQ + i];
 #pragma unroll
                 for (int t = 0; t < R4; ++t) {
-                    const float w = u4s[i * R4 + t];
+                    const float w = u4[i * R4 + t];
 #pragma unroll
                     for (int c = 0; c < PP; ++c) tmp[c][t] = fmaf(xc[c], w, tmp[c][t]);
                 }
@@ -521,9 +531,14 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
             for (int r = 0; r < R3; ++r)
 #pragma unroll
                 for (int t = 0; t < R4; ++t) {
-                    float acc = 0.f;
+                    float acc;
+                    if (ID3) {
+                        acc = tmp[r][t];
+                    } else {
+                        acc = 0.f;
 #pragma unroll
-                    for (int c = 0; c < PP; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                        for (int c = 0; c < PP; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                    }
                     y[r * R4 + t] = (OUTP == LP_BF16) ? enc_bf16(acc) : enc_f16(acc);
                 }
 #pragma unroll
@@ -543,27 +558,32 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
 
 template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO>
 bool try_pair_lp(const void* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
-                 const float* scale, int ldo, void* out, hipStream_t s, hipError_t* err) {
+                 const float* scale, int ldo, bool u3_identity, void* out, hipStream_t s, hipError_t* err) {
     if (p != PP || q != QQ || r3 != R3 || r4 != R4 || ldo != LDO) return false;
     if ((((uintptr_t)in) & 15) != 0 || (((uintptr_t)out) & 15) != 0) return false;
     const int64_t nchunks = (A + 255) / 256;
     const unsigned grid = (unsigned)(nchunks < 1024 ? nchunks : 1024);
-    hipLaunchKernelGGL((pair_lp_fixed<P, OUTP, PP, QQ, R3, R4, LDO>), dim3(grid), dim3(256), 0, s,
-                       (const typename Codec<P>::S*)in, A, U3, U4, scale, (uint16_t*)out);
+    if (u3_identity && PP == R3)
+        hipLaunchKernelGGL((pair_lp_fixed<P, OUTP, PP, QQ, R3, R4, LDO, PP == R3>), dim3(grid), dim3(256), 0, s,
+                           (const typename Codec<P>::S*)in, A, U3, U4, scale, (uint16_t*)out);
+    else
+        hipLaunchKernelGGL((pair_lp_fixed<P, OUTP, PP, QQ, R3, R4, LDO, false>), dim3(grid), dim3(256), 0, s,
+                           (const typename Codec<P>::S*)in, A, U3, U4, scale, (uint16_t*)out);
     *err = hipGetLastError();
     return true;
 }
 
 template <int P, int OUTP>
 bool pair_lp_any_fixed(const void* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
-                       const float* scale, int ldo, void* out, hipStream_t s, hipError_t* err) {
+                       const float* scale, int ldo, bool u3_identity, void* out, hipStream_t s, hipError_t* err) {
     // the image-stack fibre shapes: 3 colour channels x 2E images, R4 = 2E - 1 or the reduced ranks
-    return try_pair_lp<P, OUTP, 3, 14, 3, 8, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
-           try_pair_lp<P, OUTP, 3, 10, 3, 6, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
-           try_pair_lp<P, OUTP, 3, 6, 3, 4, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
-           try_pair_lp<P, OUTP, 3, 6, 3, 5, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
-           try_pair_lp<P, OUTP, 3, 10, 3, 9, 32>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err) ||
-           try_pair_lp<P, OUTP, 3, 14, 3, 13, 40>(in, A, p, q, U3, r3, U4, r4, scale, ldo, out, s, err);
+    return try_pair_lp<P, OUTP, 3, 14, 3, 8, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 10, 3, 6, 24>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 6, 3, 4, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 6, 3, 5, 16>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 10, 3, 9, 32>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s, err) ||
+           try_pair_lp<P, OUTP, 3, 14, 3, 13, 40>(in, A, p, q, U3, r3, U4, r4, scale, ldo, u3_identity, out, s,
+                                                   err);
 }
 
 // ---------------------------------------------------------------------------- two-mode pass (generic)
@@ -732,7 +752,7 @@ hipError_t factor_lowp(const float* U, int64_t rows, int64_t R, int64_t ldk, int
 }
 
 hipError_t pair_lowp(const void* in, int64_t A, int p, int q, const float* U3, int R3, const float* U4, int R4,
-                     int prec, const float* scale, int outp, int ldo, void* out, hipStream_t s) {
+                     int prec, const float* scale, int outp, int ldo, void* out, hipStream_t s, bool u3_identity) {
     if (p < 1 || p > 4 || q < 1 || q > 16 || R3 > p || R4 > q || ldo < R3 * R4 || ldo > 64) return hipErrorInvalidValue;
     if (outp != LP_BF16 && outp != LP_F16) return hipErrorInvalidValue;
     if (A == 0) return hipSuccess;
@@ -740,11 +760,14 @@ hipError_t pair_lowp(const void* in, int64_t A, int p, int q, const float* U3, i
         hipError_t e = hipSuccess;
         bool done = false;
         if (prec == LP_BF16 && outp == LP_BF16)
-            done = pair_lp_any_fixed<LP_BF16, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+            done = pair_lp_any_fixed<LP_BF16, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, u3_identity, out, s,
+                                                          &e);
         else if (prec == LP_F16 && outp == LP_F16)
-            done = pair_lp_any_fixed<LP_F16, LP_F16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+            done = pair_lp_any_fixed<LP_F16, LP_F16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, u3_identity, out, s,
+                                                          &e);
         else if (prec == LP_FP8 && outp == LP_BF16)
-            done = pair_lp_any_fixed<LP_FP8, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, out, s, &e);
+            done = pair_lp_any_fixed<LP_FP8, LP_BF16>(in, A, p, q, U3, R3, U4, R4, scale, ldo, u3_identity, out, s,
+                                                          &e);
         if (done) return e;
     }
     const int64_t nchunks = (A + 255) / 256;

@@ -172,6 +172,7 @@ void tucker_default_server_options(tucker_server_options* o) {
     o->init_iters = 20;
     o->seed = 0x5eedull;
     o->use_graphs = 1;
+    o->autotune = 1;
 }
 
 tucker_status tucker_server_create(const tucker_server_options* opts, tucker_server** out) {
@@ -211,6 +212,7 @@ tucker_status tucker_server_create(const tucker_server_options* opts, tucker_ser
         co.init_iters = o.init_iters;
         co.seed = o.seed;
         co.use_graphs = o.use_graphs;
+        co.autotune = o.autotune;
         tucker_ctx* c = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();

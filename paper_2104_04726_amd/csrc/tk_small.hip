@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void pair_ttm_kernel(const float* __restrict__
 // and LDS (U4 rows read as 16-byte vectors), all index arithmetic is by constants, and the next
 // chunk's 16-byte coalesced loads are issued into registers before the current chunk is mapped,
 // so HBM reads overlap the arithmetic.
-template <int P, int Q, int R3, int R4, bool EXPAND>
+template <int P, int Q, int R3, int R4, bool EXPAND, bool ID3>
 __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ in, int64_t A,
                                                       const float* __restrict__ U3,
                                                       const float* __restrict__ U4,
@@ -245,11 +245,12 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
     constexpr int VPT_IN = (NV_IN + 255) / 256;     // float4 loads per thread
     __shared__ float fin[FPB * SIN];
     __shared__ float fout[FPB * SOUT];
+    static_assert(!ID3 || P == R3, "an identity U3 keeps the mode's size");
     __shared__ float u4s[Q * R4];
     for (int i = threadIdx.x; i < Q * R4; i += 256) u4s[i] = U4[i];
     float u3[P * R3];
 #pragma unroll
-    for (int i = 0; i < P * R3; ++i) u3[i] = U3[i];
+    for (int i = 0; i < P * R3; ++i) u3[i] = ID3 ? 0.f : U3[i];
 
     const int64_t nchunks = (A + FPB - 1) / FPB;
     const int64_t full_chunks = A / FPB;
@@ -275,11 +276,19 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
             for (int u = 0; u < VPT_IN; ++u) {
                 const int i = threadIdx.x + 256 * u;
                 if (i < NV_IN) {
+                    // one division per vector; position and fibre advance by increments (LIN >= 4)
                     const float vv[4] = {pre[u].x, pre[u].y, pre[u].z, pre[u].w};
+                    const int fb = (4 * i) / LIN;
+                    int l = 4 * i - fb * LIN;
+                    float* dst = fin + fb * SIN;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int g = 4 * i + j;
-                        fin[(g / LIN) * SIN + (g % LIN)] = vv[j];
+                        dst[l] = vv[j];
+                        ++l;
+                        if (l == LIN) {
+                            l = 0;
+                            dst += SIN;
+                        }
                     }
                 }
             }
@@ -315,9 +324,14 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
                 for (int r = 0; r < R3; ++r)
 #pragma unroll
                     for (int t = 0; t < R4; ++t) {
-                        float acc = 0.f;
+                        float acc;
+                        if (ID3) {
+                            acc = tmp[r][t];
+                        } else {
+                            acc = 0.f;
 #pragma unroll
-                        for (int c = 0; c < P; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                            for (int c = 0; c < P; ++c) acc = fmaf(u3[c * R3 + r], tmp[c][t], acc);
+                        }
                         y[r * R4 + t] = acc;
                     }
             } else {
@@ -342,9 +356,14 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
                 for (int c = 0; c < P; ++c)
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
-                        float acc = 0.f;
+                        float acc;
+                        if (ID3) {
+                            acc = tmp[c][i];
+                        } else {
+                            acc = 0.f;
 #pragma unroll
-                        for (int r = 0; r < R3; ++r) acc = fmaf(u3[c * R3 + r], tmp[r][i], acc);
+                            for (int r = 0; r < R3; ++r) acc = fmaf(u3[c * R3 + r], tmp[r][i], acc);
+                        }
                         y[c * Q + i] = acc;
                     }
             }
@@ -355,10 +374,17 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
             float4* d4 = (float4*)dst;
             for (int i = threadIdx.x; i < NV_OUT; i += 256) {
                 float v[4];
+                const int fb = (4 * i) / LOUT;
+                int l = 4 * i - fb * LOUT;
+                const float* src = fout + fb * SOUT;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int g = 4 * i + j;
-                    v[j] = fout[(g / LOUT) * SOUT + (g % LOUT)];
+                    v[j] = src[l];
+                    ++l;
+                    if (l == LOUT) {
+                        l = 0;
+                        src += SOUT;
+                    }
                 }
                 d4[i] = make_float4(v[0], v[1], v[2], v[3]);
             }
@@ -696,35 +722,47 @@ bool pair_ttm_supported(int p, int q) { return p >= 1 && p <= kPairMaxP && q >= 
 namespace {
 template <int P, int Q, int R3, int R4>
 bool try_fixed(const float* in, int64_t A, int p, int q, const float* U3, int r3, const float* U4, int r4,
-               bool expand, float* out, hipStream_t s, hipError_t* err) {
+               bool expand, bool u3_identity, float* out, hipStream_t s, hipError_t* err) {
     if (p != P || q != Q || r3 != R3 || r4 != R4) return false;
     // float4 staging needs 16-byte aligned chunk starts: 256 * LIN * 4 bytes is a multiple of 16
     if ((((uintptr_t)in) & 15) != 0) return false;
     const int64_t nchunks = (A + 255) / 256;
     const unsigned grid = (unsigned)(nchunks < 1024 ? nchunks : 1024);
-    if (expand)
-        hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, true>), dim3(grid), dim3(256), 0, s, in, A, U3, U4, out);
-    else
-        hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, false>), dim3(grid), dim3(256), 0, s, in, A, U3, U4, out);
+    constexpr bool CAN_ID = (P == R3);
+    if (expand) {
+        if (CAN_ID && u3_identity)
+            hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, true, CAN_ID>), dim3(grid), dim3(256), 0, s, in, A, U3, U4,
+                               out);
+        else
+            hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, true, false>), dim3(grid), dim3(256), 0, s, in, A, U3, U4,
+                               out);
+    } else {
+        if (CAN_ID && u3_identity)
+            hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, false, CAN_ID>), dim3(grid), dim3(256), 0, s, in, A, U3,
+                               U4, out);
+        else
+            hipLaunchKernelGGL((pair_ttm_fixed<P, Q, R3, R4, false, false>), dim3(grid), dim3(256), 0, s, in, A, U3, U4,
+                               out);
+    }
     *err = hipGetLastError();
     return true;
 }
 }  // namespace
 
 hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, int R3, const float* U4,
-                    int R4, bool expand, float* out, hipStream_t s) {
+                    int R4, bool expand, float* out, hipStream_t s, bool u3_identity) {
     if (!pair_ttm_supported(p, q) || R3 > p || R4 > q) return hipErrorInvalidValue;
     if (A == 0) return hipSuccess;
     {
         // fibre shapes of the multi-exposure stacks: 3 colour channels x 2E images, R4 = 2E - 1,
         // and the reduced ranks used by the large stacks
         hipError_t e = hipSuccess;
-        if (try_fixed<3, 14, 3, 8>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
-            try_fixed<3, 10, 3, 6>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
-            try_fixed<3, 6, 3, 4>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
-            try_fixed<3, 6, 3, 5>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
-            try_fixed<3, 10, 3, 9>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e) ||
-            try_fixed<3, 14, 3, 13>(in, A, p, q, U3, R3, U4, R4, expand, out, s, &e))
+        if (try_fixed<3, 14, 3, 8>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e) ||
+            try_fixed<3, 10, 3, 6>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e) ||
+            try_fixed<3, 6, 3, 4>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e) ||
+            try_fixed<3, 6, 3, 5>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e) ||
+            try_fixed<3, 10, 3, 9>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e) ||
+            try_fixed<3, 14, 3, 13>(in, A, p, q, U3, R3, U4, R4, expand, u3_identity, out, s, &e))
             return e;
     }
     const int Lin = expand ? R3 * R4 : p * q;

@@ -1,0 +1,121 @@
+// The library's autotuner: launch choices measured on the device on first use and cached.
+//
+// A choice is keyed by the operation and the shape that determines it (and the device).  The first
+// call of a key in the process fixes its choice for the rest of the process: when tuning is on for the
+// calling thread (tucker_options.autotune) and the stream is not being captured into a graph, every
+// candidate is launched twice on the caller's stream, the second launch timed with HIP events, and the
+// fastest is kept; otherwise the heuristic choice is kept.  Every later call with the same key reuses
+// it, so within a process a shape's results do not depend on which calls ran before or beside it.
+// Candidates of one key must leave identical results or results of one fixed reduction order each,
+// and their outputs must be idempotent (stores, not accumulations).
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "tk_common.h"
+
+namespace tk {
+namespace {
+
+using Key = std::tuple<int, int, int64_t, int64_t, int64_t, int64_t, int64_t>;   // op, device, shape...
+
+struct Entry {
+    int choice;
+    std::vector<double> ms;     // measured time of every candidate (ms)
+};
+
+std::mutex g_mu;
+std::map<Key, Entry> g_table;
+thread_local bool t_enabled = false;
+
+}  // namespace
+
+void tune_set_enabled(bool on) { t_enabled = on; }
+bool tune_enabled() { return t_enabled; }
+
+int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStream_t s,
+                const std::function<hipError_t(int)>& launch, hipError_t* err) {
+    *err = hipSuccess;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const Key key{op, dev, shape[0], shape[1], shape[2], shape[3], shape[4]};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_table.find(key);
+        if (it != g_table.end()) return it->second.choice;
+    }
+    auto keep = [&](const Entry& en) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_table.find(key);                      // another thread may have fixed it meanwhile
+        if (it != g_table.end()) return it->second.choice;
+        g_table.emplace(key, en);
+        return en.choice;
+    };
+    bool timed = t_enabled && ncand > 1;
+    if (timed) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            timed = false;
+        }
+    }
+    if (!timed) return keep(Entry{heuristic, {}});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipGetLastError();
+        return keep(Entry{heuristic, {}});
+    }
+    Entry en{heuristic, std::vector<double>(ncand, -1.0)};
+    double best = 0.0;
+    for (int c = 0; c < ncand && *err == hipSuccess; ++c) {
+        *err = launch(c);                                   // warm-up (code objects, caches)
+        if (*err != hipSuccess) break;
+        *err = hipEventRecord(e0, s);
+        if (*err == hipSuccess) *err = launch(c);
+        if (*err == hipSuccess) *err = hipEventRecord(e1, s);
+        if (*err == hipSuccess) *err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, e0, e1);
+        if (*err != hipSuccess) break;
+        en.ms[c] = ms;
+        if (c == 0 || ms < best) {
+            best = ms;
+            en.choice = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (*err != hipSuccess) return heuristic;
+    return keep(en);
+}
+
+std::string tune_dump() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::ostringstream os;
+    for (const auto& kv : g_table) {
+        const Key& k = kv.first;
+        os << "op " << std::get<0>(k) << " dev " << std::get<1>(k) << " shape " << std::get<2>(k) << ' '
+           << std::get<3>(k) << ' ' << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k)
+           << " choice " << kv.second.choice << " ms";
+        for (double m : kv.second.ms) os << ' ' << m;
+        if (kv.second.ms.empty()) os << " (heuristic)";
+        os << '\n';
+    }
+    return os.str();
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+}
+
+size_t tune_size() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_table.size();
+}
+
+}  // namespace tk
