@@ -313,6 +313,8 @@ def main():
                     help="cold-start orthogonal-iteration steps of the T-HOSVD start")
     ap.add_argument("--start", default="thosvd", choices=["thosvd", "sthosvd"],
                     help="initialisation: truncated HOSVD (default) or the sequentially truncated HOSVD")
+    ap.add_argument("--pp-tol", type=float, default=0.0,
+                    help="pairwise-perturbation sweeps once the factors settle to this subspace distance (0: off)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
     ap.add_argument("--graphs", action="store_true",
@@ -353,10 +355,10 @@ def main():
     if args.graphs:
         side = torch.cuda.Stream()
         ctx = tk.Context(0, stream=side, timing=False, precision=args.precision, refine_sweeps=1,
-                         init_iters=args.init_iters, use_graphs=True, start=args.start)
+                         init_iters=args.init_iters, use_graphs=True, start=args.start, pp_tol=args.pp_tol)
     else:
         ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters,
-                         start=args.start)
+                         start=args.start, pp_tol=args.pp_tol)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
@@ -422,6 +424,7 @@ def main():
                    "precision": args.precision,
                    "sweeps_per_step": sweeps, "fit": round(r.fit, 9),
                    "orth_second_passes": r.stats.get("orth_second_passes"),
+                   "pp_tol": args.pp_tol, "pp_sweeps": r.stats.get("pp_sweeps"),
                    "init_ms": round(init_ms / args.steps, 3), "sweeps_ms": round(sweeps_ms / args.steps, 3)},
         "roofline": roof,
         "stages": stages,

@@ -106,6 +106,16 @@ typedef struct {
                                     on first use and the fastest kept (tucker_autotune_dump);
                                     0: such choices take the built-in heuristic.  Either way the
                                     first call of a shape fixes its choice for the process.     */
+    double pp_tol;               /* > 0: pairwise-perturbation sweeps (Sec. III-B, eq. (9)-(13)).
+                                    Ordinary sweeps run until the largest subspace distance
+                                    ||U U^T - V V^T||_F / sqrt(2R) between consecutive factors is
+                                    below pp_tol; then, around those factors, the tensors of the
+                                    updates are taken to first order in the factor changes from
+                                    operators formed once (X is not read), while every factor stays
+                                    within pp_tol of the reference; the returned core and fit are
+                                    exact.  FP32 sweeps (tol = 0) of order-4 stacks whose third
+                                    mode is kept at full rank (identity factor) only, else
+                                    TUCKER_ERR_UNSUPPORTED.  0 (default): ordinary sweeps.        */
 } tucker_options;
 
 /* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack
@@ -144,6 +154,8 @@ typedef struct {
     int oi_steps_sweeps;         /* orthogonal-iteration steps of the sweeps (all large modes) */
     double oi_residual_max;      /* inner_tol > 0: largest final ||S U - U U^T S U||_F / ||S||_F
                                     over the updates of the call (0 otherwise)                */
+    int pp_sweeps;               /* pairwise-perturbation sweeps among the sweeps (pp_tol > 0) */
+    int pp_refs;                 /* reference points (operator sets) formed                   */
     size_t workspace_bytes;      /* device workspace held by the context                      */
     double stage_ms[TUCKER_NUM_STAGES];   /* summed GPU time per stage (timing = 1)           */
     int stage_calls[TUCKER_NUM_STAGES];   /* number of timed occurrences per stage            */

@@ -35,6 +35,7 @@ class Options(C.Structure):
         ("wait_spin_limit", C.c_int64),
         ("start", C.c_int),
         ("autotune", C.c_int),
+        ("pp_tol", C.c_double),
     ]
 
 
@@ -52,6 +53,8 @@ class Stats(C.Structure):
         ("oi_steps_init", C.c_int),
         ("oi_steps_sweeps", C.c_int),
         ("oi_residual_max", C.c_double),
+        ("pp_sweeps", C.c_int),
+        ("pp_refs", C.c_int),
         ("workspace_bytes", C.c_size_t),
         ("stage_ms", C.c_double * 12),
         ("stage_calls", C.c_int * 12),

@@ -174,6 +174,16 @@ struct Plan {
     double* fits = nullptr;      // max_iters + 1
     int* shifts = nullptr;
     float* Xh = nullptr;         // explicit reconstruction when the residual cannot be fused
+    // pairwise perturbation (tree shapes): operators at the reference factors, the reference
+    // factors, their changes, and the scratch of the factor alignment
+    bool pp = false;
+    float *Y0p = nullptr, *Y1p = nullptr, *T12p = nullptr, *Zp = nullptr, *PPtmp = nullptr;
+    float* U32p[TUCKER_MAX_ORDER]{};
+    double* U64p[TUCKER_MAX_ORDER]{};
+    double* U64prev[TUCKER_MAX_ORDER]{};
+    float* dU[TUCKER_MAX_ORDER]{};
+    double *NS_X = nullptr, *NS_B = nullptr, *NS_D = nullptr, *NS_T = nullptr, *NS_U = nullptr;
+    double* ppdist = nullptr;    // squared Frobenius norms of U^T V, one per mode
 };
 
 int64_t max_large_s(const Plan& p) {
@@ -359,6 +369,29 @@ void build_plan(Plan& p, Arena& a) {
     p.fits = a.take<double>(p.max_iters + p.refine + 2);
     p.shifts = a.take<int>(8);
     if (!p.tree) p.Xh = (p.kind[0] == LARGE && p.s[0] > kSmallMode) ? nullptr : a.take<float>(Xn);
+    if (p.pp) {
+        const int64_t s0 = p.s[0], s1 = p.s[1], L = p.s[2] * p.s[3], R23 = p.R[2] * p.R[3];
+        p.Y0p = a.take<float>(s0 * p.R[1] * R23);
+        p.Y1p = a.take<float>(p.R[0] * s1 * R23);
+        p.T12p = a.take<float>(p.R[0] * p.R[1] * L);
+        p.Zp = a.take<float>(s0 * p.R[1] * L);
+        p.PPtmp = a.take<float>(std::max(s0 * p.R[1] * R23, p.R[0] * s1 * R23));
+        int64_t rr = 1, sr = 1;
+        for (int n = 0; n < N; ++n) {
+            p.U32p[n] = a.take<float>(p.s[n] * p.R[n]);
+            p.U64p[n] = a.take<double>(p.s[n] * p.R[n]);
+            p.U64prev[n] = a.take<double>(p.s[n] * p.R[n]);
+            p.dU[n] = a.take<float>(p.s[n] * p.R[n]);
+            rr = std::max(rr, p.R[n] * p.R[n]);
+            sr = std::max(sr, p.s[n] * p.R[n]);
+        }
+        p.NS_X = a.take<double>(rr);
+        p.NS_B = a.take<double>(rr);
+        p.NS_D = a.take<double>(rr);
+        p.NS_T = a.take<double>(rr);
+        p.NS_U = a.take<double>(sr);
+        p.ppdist = a.take<double>(2 * TUCKER_MAX_ORDER + kSumsqBlocks);
+    }
     p.has_alt = p.tree && p.kind[0] == LARGE && p.kind[1] == LARGE;
     if (p.has_alt) {
         const int64_t s0 = p.s[0], R0 = p.R[0];
@@ -1157,6 +1190,185 @@ void sweep_tree(Run& r) {
                     p.ident[2]));
 }
 
+// ------------------------------------------------------------------ pairwise perturbation
+// Sec. III-B, eq. (9)-(13): around reference factors S_p (the factors when the sweeps had nearly
+// settled), the tensor of an update is taken to first order in dS = S - S_p,
+//   Y~(n) = Y_p(n) + sum_{i != n} Y_p(i,n) x_i dS(i)^T,
+// with the operators Y_p(n) = X x_{l != n} S_p(l)^T and Y_p(i,n) = X x_{j not in {i,n}} S_p(j)^T formed once
+// per reference point; perturbation sweeps read only them, never X.  For the image stacks (modes
+// (H, W, C, I), the colour mode kept at full rank with the identity factor, so dS(3) = 0):
+//   Y_p(1) = T34 x_2 S2^T (Y0p), Y_p(1,2) = T34 = X x_3 S3^T x_4 S4^T, Y_p(1,4) = Z = X x_2 S2^T,
+//   Y_p(2) = T1 x_3 x_4 (Y1p), Y_p(2,4) = T1 = X x_1 S1^T, Y_p(4) = T12 = T1 x_2 S2^T,
+// so Y~(1) = Y0p + T34 x_2 dS2^T + Z x_4 dS4^T, Y~(2) = Y1p + T34 x_1 dS1^T + T1 x_4 dS4^T and
+// Y~(4) = T12p + Z x_1 dS1^T + T1 x_2 dS2^T.  Each new factor is represented by the orthonormal basis
+// of its subspace closest to the reference (orthogonal Procrustes, the polar factor of U^T S_p by
+// Newton-Schulz iteration in FP64).  The sweeps switch between ordinary and perturbation ones on the
+// subspace distance d(U, V) = ||U U^T - V V^T||_F / sqrt(2R) = sqrt(1 - ||U^T V||_F^2 / R).
+
+// out += in x_n U^T (U: dims[n] x R) by the FP32 matrix cores, accumulating into out
+void ttm_add(Run& r, const float* in, const int64_t* dims, int N, int n, const float* U, int64_t R, float* out) {
+    const int64_t A = prod(dims, 0, n), K = dims[n], B = prod(dims, n + 1, N);
+    GemmArgs g{};
+    g.alpha = 1.0;
+    if (B == 1) {
+        g.M = A;
+        g.N = R;
+        g.K = K;
+        g.a = plain(in, K);
+        g.b = plain(U, R);
+        g.c = plain(out, R);
+        TK_HIP(gemm_f32(g, MK, KM, EPI_ADD, false, r.st));
+    } else {
+        g.M = R;
+        g.N = A * B;
+        g.K = K;
+        g.a = plain(U, R);
+        g.b = folded(in, B, B, K * B);
+        g.c = folded(out, B, B, R * B);
+        TK_HIP(gemm_f32(g, KM, KM, EPI_ADD, false, r.st));
+    }
+}
+
+// C (M x N, FP64) = A^T B for A (K x M) and B (K x N), FP64 row-major
+void gemm_tn64(Run& r, const double* A, const double* B, int64_t K, int64_t M, int64_t N, double* C) {
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.a = plain(A, M);
+    g.b = plain(B, N);
+    g.c = plain(C, N);
+    TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+}
+// C (M x N) = A B for A (M x K) and B (K x N), FP64
+void gemm_nn64(Run& r, const double* A, const double* B, int64_t M, int64_t K, int64_t N, double* C) {
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.a = plain(A, K);
+    g.b = plain(B, N);
+    g.c = plain(C, N);
+    TK_HIP(gemm_f64(g, MK, KM, EPI_STORE, false, false, r.st));
+}
+
+constexpr int kNewtonSchulzSteps = 12;   // quadratic convergence for singular values of U^T S_p above ~0.1
+
+// U_n <- U_n Q with Q the polar factor of U_n^T S_p(n): the basis of span(U_n) closest to S_p(n)
+void pp_align(Run& r, int n) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n], R = p.R[n];
+    gemm_tn64(r, p.U64[n], p.U64p[n], s, R, R, p.NS_X);
+    for (int it = 0; it < kNewtonSchulzSteps; ++it) {
+        gemm_tn64(r, p.NS_X, p.NS_X, R, R, R, p.NS_B);          // B = X^T X
+        TK_HIP(ns_step(p.NS_B, p.NS_D, R, r.st));               // D = 1.5 I - 0.5 B
+        gemm_nn64(r, p.NS_X, p.NS_D, R, R, R, p.NS_T);          // X <- X D
+        std::swap(p.NS_X, p.NS_T);
+    }
+    gemm_nn64(r, p.U64[n], p.NS_X, s, R, R, p.NS_U);
+    TK_HIP(hipMemcpyAsync(p.U64[n], p.NS_U, s * R * sizeof(double), hipMemcpyDeviceToDevice, r.st));
+    TK_HIP(f64_to_f32(p.U64[n], p.U32[n], s * R, r.st));
+}
+
+// max over the modes of d(U_n, V_n) for V = the reference (against_ref) or the previous sweep's factors
+double pp_distance(Run& r, bool against_ref) {
+    Plan& p = r.p;
+    for (int n = 0; n < p.N; ++n) {
+        const int64_t s = p.s[n], R = p.R[n];
+        gemm_tn64(r, p.U64[n], against_ref ? p.U64p[n] : p.U64prev[n], s, R, R, p.NS_B);
+        TK_HIP(sumsq_f64(p.NS_B, R * R, p.ppdist + 2 * TUCKER_MAX_ORDER, kSumsqBlocks, p.ppdist + n, r.st));
+    }
+    double h[TUCKER_MAX_ORDER] = {};
+    TK_HIP(hipMemcpyAsync(h, p.ppdist, p.N * sizeof(double), hipMemcpyDeviceToHost, r.st));
+    TK_HIP(hipStreamSynchronize(r.st));
+    double d = 0.0;
+    for (int n = 0; n < p.N; ++n) d = std::max(d, std::sqrt(std::max(1.0 - h[n] / (double)p.R[n], 0.0)));
+    return d;
+}
+
+// the reference point: current factors and the operators around them
+void pp_init(Run& r) {
+    Plan& p = r.p;
+    const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3], L = s2 * s3;
+    const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3], R23 = R2 * R3;
+    if (!p.ident[2]) throw Fail{TUCKER_ERR_UNSUPPORTED, "pairwise perturbation needs the identity colour factor"};
+    for (int n = 0; n < p.N; ++n) {
+        TK_HIP(hipMemcpyAsync(p.U32p[n], p.U32[n], p.s[n] * p.R[n] * sizeof(float), hipMemcpyDeviceToDevice, r.st));
+        TK_HIP(hipMemcpyAsync(p.U64p[n], p.U64[n], p.s[n] * p.R[n] * sizeof(double), hipMemcpyDeviceToDevice, r.st));
+    }
+    TK_HIP(pair_ttm(r.X, s0 * s1, (int)s2, (int)s3, p.U32p[2], (int)R2, p.U32p[3], (int)R3, false, p.T34, r.st,
+                    true));
+    int64_t d34[3] = {s0, s1, R23};
+    ttm(r, p.T34, d34, 3, 1, p.U32p[1], R1, false, p.Y0p);
+    int64_t dx[3] = {s0, s1, L};
+    ttm(r, r.X, dx, 3, 0, p.U32p[0], R0, false, p.T1);
+    ttm(r, r.X, dx, 3, 1, p.U32p[1], R1, false, p.Zp);
+    TK_HIP(pair_ttm(p.T1, R0 * s1, (int)s2, (int)s3, p.U32p[2], (int)R2, p.U32p[3], (int)R3, false, p.Y1p, r.st,
+                    true));
+    int64_t d1[3] = {R0, s1, L};
+    ttm(r, p.T1, d1, 3, 1, p.U32p[1], R1, false, p.T12p);
+}
+
+// one perturbation sweep: modes 1, 2 and 4 from the first-order tensors, the core from Y~(4)
+void pp_sweep(Run& r) {
+    Plan& p = r.p;
+    const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3], L = s2 * s3;
+    const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3], R23 = R2 * R3;
+    auto delta = [&](int n) { TK_HIP(diff_f32(p.U32[n], p.U32p[n], p.dU[n], p.s[n] * p.R[n], r.st)); };
+    const bool m4 = p.kind[3] != FIXED;
+    delta(1);
+    if (m4) delta(3);
+    // mode 1: Y~(1) = Y0p + T34 x_2 dS2^T + Z x_4 dS4^T (s0, R1, R3 R4)
+    TK_HIP(hipMemcpyAsync(p.Y0, p.Y0p, s0 * R1 * R23 * sizeof(float), hipMemcpyDeviceToDevice, r.st));
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_Y1);
+        int64_t d34[3] = {s0, s1, R23};
+        ttm_add(r, p.T34, d34, 3, 1, p.dU[1], R1, p.Y0);
+        if (m4) {
+            TK_HIP(small_ttm(p.Zp, s0 * R1 * s2, s3, 1, p.dU[3], R3, false, p.PPtmp, r.st));
+            TK_HIP(axpy_f32(p.PPtmp, p.Y0, s0 * R1 * R23, r.st));
+        }
+    }
+    direct_update(r, p.Y0, 1, s0, R1 * R23, 0, TUCKER_STAGE_GRAM_1, TUCKER_STAGE_OI_1);
+    pp_align(r, 0);
+    delta(0);
+    // mode 2: Y~(2) = Y1p + T34 x_1 dS1^T + T1 x_4 dS4^T (R0, s1, R3 R4)
+    TK_HIP(hipMemcpyAsync(p.Y1, p.Y1p, R0 * s1 * R23 * sizeof(float), hipMemcpyDeviceToDevice, r.st));
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_Y2);
+        int64_t d34[2] = {s0, s1 * R23};
+        ttm_add(r, p.T34, d34, 2, 0, p.dU[0], R0, p.Y1);
+        if (m4) {
+            TK_HIP(small_ttm(p.T1, R0 * s1 * s2, s3, 1, p.dU[3], R3, false, p.PPtmp, r.st));
+            TK_HIP(axpy_f32(p.PPtmp, p.Y1, R0 * s1 * R23, r.st));
+        }
+    }
+    direct_update(r, p.Y1, R0, s1, R23, 1, TUCKER_STAGE_GRAM_2, TUCKER_STAGE_OI_2);
+    pp_align(r, 1);
+    delta(1);
+    // mode 4: Y~(4) = T12p + Z x_1 dS1^T + T1 x_2 dS2^T (R0, R1, s3 s4)
+    TK_HIP(hipMemcpyAsync(p.T12, p.T12p, R0 * R1 * L * sizeof(float), hipMemcpyDeviceToDevice, r.st));
+    {
+        StageTimer t(r, TUCKER_STAGE_TTM_C2);
+        int64_t dz[2] = {s0, R1 * L};
+        ttm_add(r, p.Zp, dz, 2, 0, p.dU[0], R0, p.T12);
+        int64_t d1[3] = {R0, s1, L};
+        ttm_add(r, p.T1, d1, 3, 1, p.dU[1], R1, p.T12);
+    }
+    if (m4) {
+        StageTimer t(r, TUCKER_STAGE_SMALL);
+        TK_HIP(fibre_gram(p.T12, R0 * R1, (int)L, p.Fpart, kFibreGramBlocks, p.F, r.st));
+        TK_HIP(pair_mode_gram(p.F, (int)s2, (int)s3, p.U64[2], (int)R2, 4, p.S64, r.st));
+        update_factor(r, 3, false);
+        pp_align(r, 3);
+    }
+    StageTimer t(r, TUCKER_STAGE_CORE);
+    TK_HIP(pair_ttm(p.T12, R0 * R1, (int)s2, (int)s3, p.U32[2], (int)R2, p.U32[3], (int)R3, false, p.G, r.st,
+                    true));
+}
+
 // ------------------------------------------------------------------ reduced-precision sweep
 // The same tree sweep as sweep_tree with every dense contraction on the 16-/8-bit matrix cores
 // (FP32 accumulation) and the intermediates T34, Y0, Y1, T1 stored in the 16-bit type; the
@@ -1418,7 +1630,7 @@ tucker_status validate_args(int ndim, const int64_t* dims, const int64_t* ranks,
 }
 
 void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int max_iters, int prec = 0,
-               int refine = 0) {
+               int refine = 0, bool pp = false) {
     p.N = ndim;
     p.max_iters = max_iters;
     p.refine = prec ? refine : 0;
@@ -1433,6 +1645,11 @@ void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int
     if (prec != 0 && !(p.tree && p.kind[0] == LARGE && p.kind[1] == LARGE))
         throw Fail{TUCKER_ERR_UNSUPPORTED,
                    "reduced precision needs an order-4 tensor with two large leading modes and small trailing ones"};
+    p.pp = pp;
+    if (pp && !(p.tree && prec == 0 && p.kind[0] == LARGE && p.kind[1] == LARGE && p.kind[2] == FIXED))
+        throw Fail{TUCKER_ERR_UNSUPPORTED,
+                   "pairwise perturbation needs FP32 sweeps of an order-4 stack with two large leading modes, a "
+                   "full-rank third mode and a small fourth one"};
 }
 
 size_t plan_bytes(Plan& p) {
@@ -1709,6 +1926,7 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
     if (opts) o = *opts;
     if (o.inner_iters < 1 || o.init_iters < 1 || o.refine_sweeps < 0 || o.precision < TUCKER_FP32 ||
         o.precision > TUCKER_FP8_E4M3 || o.device < 0 || !(o.inner_tol >= 0.0) || o.wait_spin_limit < 0 ||
+        !(o.pp_tol >= 0.0) ||
         (o.start != TUCKER_START_THOSVD && o.start != TUCKER_START_STHOSVD))
         return TUCKER_ERR_INVALID_ARG;
     int count = 0;
@@ -1792,7 +2010,10 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         Run r{ctx, Plan{}, ctx->stream, tensor};
         Plan& p = r.p;
         ctx->stats = tucker_stats{};
-        make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps);
+        if (ctx->opt.pp_tol > 0.0 && tol > 0.0)
+            throw Fail{TUCKER_ERR_UNSUPPORTED, "pairwise perturbation runs a fixed number of sweeps (tol = 0)"};
+        make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps,
+                  ctx->opt.pp_tol > 0.0);
         bind(ctx, p);
         const hipStream_t s = r.st;
         reset_counters(r);
@@ -1859,7 +2080,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         // lands in fits[k] through a device-side counter.  Needs a capturable (non-null) stream,
         // no per-sweep host read (tol = 0) and no stage timers.
         const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0 &&
-                            !(r.inner_tol() > 0.0);
+                            !(r.inner_tol() > 0.0) && !p.pp;
         GraphHold hold{s};
         if (graphs) {
             TK_HIP(tk_set_int(p.shifts + 3, 1, s));
@@ -1880,9 +2101,33 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
             for (int k = 1; k <= max_iters; ++k) TK_HIP(hipGraphLaunch(hold.exec, s));
             done = max_iters;
         }
+        // pairwise perturbation: ordinary sweeps until the factors settle, then perturbation sweeps
+        // around the reference point while they stay near it (switching on the subspace distance)
+        bool pp_mode = false, last_pp = false;
+        int pp_sweeps = 0, pp_refs = 0;
         for (int k = 1; k <= max_iters && !graphs; ++k) {
-            one_sweep();
+            if (p.pp && !pp_mode)
+                for (int n = 0; n < p.N; ++n)
+                    TK_HIP(hipMemcpyAsync(p.U64prev[n], p.U64[n], p.s[n] * p.R[n] * sizeof(double),
+                                          hipMemcpyDeviceToDevice, s));
+            if (pp_mode)
+                pp_sweep(r);
+            else
+                one_sweep();
             sweep_fit(p.fits + k);
+            last_pp = pp_mode;
+            if (p.pp && k < max_iters) {
+                if (pp_mode) {
+                    ++pp_sweeps;
+                    if (pp_distance(r, true) > ctx->opt.pp_tol) pp_mode = false;
+                } else if (pp_distance(r, false) < ctx->opt.pp_tol) {
+                    pp_init(r);
+                    pp_mode = true;
+                    ++pp_refs;
+                }
+            } else if (pp_mode) {
+                ++pp_sweeps;
+            }
             done = k;
             if (tol > 0.0) {
                 TK_HIP(hipMemcpyAsync(hf.data(), p.fits + k - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1900,6 +2145,9 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
             core_norm_and_fit(r, p.fits + done + k);
         }
         r.inner_override = 0;
+        if (last_pp) core_from_x(r);     // the returned core is exact, not the first-order one
+        ctx->stats.pp_sweeps = pp_sweeps;
+        ctx->stats.pp_refs = pp_refs;
         TK_HIP(hipEventRecord(ctx->ev[2], s));
         expand_chain(r, p.G, p.U32, nullptr, tensor);
         TK_HIP(fit_from_resid(p.scal + 0, p.scal + 2, p.scal + 3, s));

@@ -99,3 +99,42 @@ hipError_t sqrt_clamp(const double* lam, int64_t n, double* out, hipStream_t s) 
 }
 
 }  // namespace tk
+
+// ---------------------------------------------------------------- elementwise helpers of the
+// pairwise-perturbation sweep (Sec. III-B, eq. (11)) and its factor alignment
+namespace tk {
+namespace {
+__global__ __launch_bounds__(256) void axpy_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] += x[i];
+}
+__global__ __launch_bounds__(256) void diff_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                   float* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) out[i] = a[i] - b[i];
+}
+// D = 1.5 I - 0.5 B (n x n), the Newton-Schulz step matrix of the polar factor
+__global__ __launch_bounds__(256) void ns_step_kernel(const double* __restrict__ B, double* __restrict__ D, int64_t n) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / n, j = e % n;
+        D[e] = (i == j ? 1.5 : 0.0) - 0.5 * B[e];
+    }
+}
+unsigned grid_n(int64_t n) {
+    const int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+}  // namespace
+
+hipError_t axpy_f32(const float* x, float* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(grid_n(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+hipError_t diff_f32(const float* a, const float* b, float* out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(diff_kernel, dim3(grid_n(n)), dim3(256), 0, s, a, b, out, n);
+    return hipGetLastError();
+}
+hipError_t ns_step(const double* B, double* D, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(ns_step_kernel, dim3(grid_n(n * n)), dim3(256), 0, s, B, D, n);
+    return hipGetLastError();
+}
+}  // namespace tk

@@ -197,6 +197,10 @@ hipError_t quantize_uniform(const float* x, int64_t n, int bits, float* amax_scr
                             float* step, hipStream_t s);
 // out[i] = sqrt(max(lam[i], 0))
 hipError_t sqrt_clamp(const double* lam, int64_t n, double* out, hipStream_t s);
+// y += x; out = a - b (FP32); D = 1.5 I - 0.5 B (FP64, n x n)
+hipError_t axpy_f32(const float* x, float* y, int64_t n, hipStream_t s);
+hipError_t diff_f32(const float* a, const float* b, float* out, int64_t n, hipStream_t s);
+hipError_t ns_step(const double* B, double* D, int64_t n, hipStream_t s);
 
 // Jacobi eigen-decomposition of a symmetric n x n (n <= 64) fp64 matrix; writes the leading
 // r eigenvectors (descending) to U64 (n x r fp64) and U32 (n x r fp32, nullable), all
