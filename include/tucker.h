@@ -101,8 +101,9 @@ typedef struct {
                                     finishes normally and the call returns TUCKER_ERR_DEVICE.
                                     Tiny values exist to exercise that error path.            */
     tucker_start start;          /* initialisation of the factors (default TUCKER_START_THOSVD) */
-    int autotune;                /* 1: launch choices not yet fixed in this process (FP32 product
-                                    tile shape, FP64 Gram split count) are measured on the device
+    int autotune;                /* 1: launch choices not yet fixed in this process (FP32 and
+                                    reduced-precision product tile shapes, FP64 Gram split
+                                    count) are measured on the device
                                     on first use and the fastest kept (tucker_autotune_dump);
                                     0: such choices take the built-in heuristic.  Either way the
                                     first call of a shape fixes its choice for the process.     */
@@ -400,14 +401,21 @@ tucker_status tucker_server_get_stats(tucker_server* srv, tucker_server_stats* o
 tucker_status tucker_server_destroy(tucker_server* srv);
 
 /* ---- Autotuner ----
- * Launch choices (the output tile shape of the FP32 mode products, the split count of the FP64 Grams)
- * are kept per (operation, shape, device) for the life of the process; see tucker_options.autotune.
+ * Launch choices are kept per (operation, shape, device) for the life of the process; see
+ * tucker_options.autotune.  Operations: 1 = output tile of the FP32 mode products (2 candidates),
+ * 2 = split count of the FP64 Grams (4), 3 = LDS staging (one or two stages) of the BF16/FP16/FP8
+ * products and Grams (2).  The candidates of operation 3 give bit-identical results.
  * tucker_autotune_dump writes one line per choice ("op <id> dev <d> shape <5 numbers> choice <c> ms
  * <time per candidate>", "(heuristic)" when nothing was timed) into buf (host, len bytes, always
  * NUL-terminated when len > 0) and the full length including the NUL to *needed (nullable).
  * tucker_autotune_clear forgets every choice (later calls choose again). */
 tucker_status tucker_autotune_dump(char* buf, size_t len, size_t* needed);
 tucker_status tucker_autotune_clear(void);
+/* Makes every later call of operation op (1..3) in this process take candidate `choice` (counted
+ * from 0; a choice beyond an operation's candidates takes the last one), bypassing the kept table;
+ * choice < 0 lifts the override.  For comparing candidates and for reproducing a run on another
+ * device.  TUCKER_ERR_INVALID_ARG for an unknown op. */
+tucker_status tucker_autotune_force(int op, int choice);
 
 /* ---- Diagnostics ---- */
 const char* tucker_status_string(tucker_status s);

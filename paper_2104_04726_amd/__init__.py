@@ -330,6 +330,12 @@ def autotune_clear() -> None:
     _lib.lib().tucker_autotune_clear()
 
 
+def autotune_force(op: int, choice: int) -> None:
+    """Every later call of autotuner operation `op` (1 FP32 tiles, 2 FP64 Gram splits, 3 reduced-precision
+    tiles) takes candidate `choice`; a negative choice lifts the override."""
+    _check(_lib.lib().tucker_autotune_force(int(op), int(choice)))
+
+
 _default = {}
 
 

@@ -157,6 +157,8 @@ def _declare(lib):
     lib.tucker_autotune_dump.restype = C.c_int
     lib.tucker_autotune_clear.argtypes = []
     lib.tucker_autotune_clear.restype = C.c_int
+    lib.tucker_autotune_force.argtypes = [C.c_int, C.c_int]
+    lib.tucker_autotune_force.restype = C.c_int
     lib.tucker_status_string.argtypes = [C.c_int]
     lib.tucker_status_string.restype = C.c_char_p
     lib.tucker_last_error.argtypes = [v]

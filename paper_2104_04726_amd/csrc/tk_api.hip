@@ -2615,6 +2615,10 @@ tucker_status tucker_autotune_clear(void) {
     return TUCKER_OK;
 }
 
+tucker_status tucker_autotune_force(int op, int choice) {
+    return tune_force(op, choice) ? TUCKER_OK : TUCKER_ERR_INVALID_ARG;
+}
+
 const char* tucker_status_string(tucker_status s) {
     switch (s) {
         case TUCKER_OK: return "ok";

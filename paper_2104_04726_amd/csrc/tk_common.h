@@ -165,7 +165,7 @@ hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U
 // ---------------------------------------------------------------------------------------
 // Autotuner (tk_tune.hip): measured launch choices cached per (operation, shape, device)
 // ---------------------------------------------------------------------------------------
-enum TuneOp { kTuneF32Tile = 1, kTuneGramSplit = 2 };
+enum TuneOp { kTuneF32Tile = 1, kTuneGramSplit = 2, kTuneLpTile = 3 };
 void tune_set_enabled(bool on);     // this thread's calls may time new keys
 bool tune_enabled();
 // The cached choice for (op, device, shape), else, when tuning is enabled and the stream is not
@@ -175,6 +175,8 @@ int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStr
                 const std::function<hipError_t(int)>& launch, hipError_t* err);
 std::string tune_dump();
 void tune_clear();
+// candidate `choice` for every later call of op (< 0: none); false for an unknown op
+bool tune_force(int op, int choice);
 size_t tune_size();
 // RAII: tuning on for this thread while in scope (restores the previous state)
 struct TuneScope {

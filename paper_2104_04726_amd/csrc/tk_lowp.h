@@ -24,8 +24,16 @@ struct LpGemmArgs {
 // (ob == KM: desc rows k, columns n) or k-contiguous (ob == MK: desc rows n, columns k).
 // Operands in the storage type prec; output float (outp == LP_F32OUT) or BF16/FP16.
 // FP8 is provided for ob == KM with a BF16 output (the full-tensor product).
+// Outputs: float, or the 16-bit type of the sweep's intermediates (BF16 for BF16 and FP8 operands,
+// FP16 for FP16 operands); other combinations return hipErrorInvalidValue.
 hipError_t gemm_lp(const LpGemmArgs& g, int prec, Orient ob, int outp, hipStream_t s);
-int64_t gemm_lp_blocks(const LpGemmArgs& g);
+
+// k step of the GEMM's tiles (k_split must be a multiple of it or cover all of K)
+constexpr int kLpGemmK = 64;
+// the per-type instantiations behind gemm_lp (vec: 8-element vector loads are legal)
+hipError_t gemm_lp_bf16(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
+hipError_t gemm_lp_f16(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
+hipError_t gemm_lp_fp8(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
 
 // out[i] = enc(x[i] / scale[i % L]) (scale nullable)
 hipError_t to_lowp(const float* x, int64_t n, int prec, int L, const float* scale, void* out, hipStream_t s);

@@ -9,334 +9,11 @@
 // (bias 7, no infinities, largest finite 448); values are divided by a per-slice FP32 scale
 // (amax / 448) before the RNE conversion, with saturation at +-448.
 //
-// GEMM tiling: 256 threads = 4 waves in a 2x2 grid over a 128 x 128 output tile; each wave owns
-// 4 x 4 MFMA tiles of 16 x 16 and steps k by 32.  Both operands sit in LDS with k contiguous
-// ([row][k], rows padded by 16 bytes), so a lane's eight consecutive k values are one 16-byte
-// (8-byte for FP8) LDS read.  A is always k-contiguous in memory (transposed factor copies, Gram
-// operands).  B is either k-contiguous (Grams) or n-contiguous (mode products over a tensor): the
-// latter is loaded as 4 (k) x 8 (n) register blocks and transposed on the way into LDS.  The next
-// k-tile is prefetched into registers while the current one is multiplied.
-#include "tk_common.h"
-#include "tk_lowp.h"
+// The GEMM itself lives in tk_lowp_gemm.h (one translation unit per storage type).
+#include "tk_lowp_impl.h"
 
 namespace tk {
 namespace {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-// ---------------------------------------------------------------------------- encodings
-__device__ __forceinline__ uint16_t enc_bf16(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                            // RNE
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float dec_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-__device__ __forceinline__ uint16_t enc_f16(float x) {
-    _Float16 h = (_Float16)x;                 // RNE conversion instruction
-    return __builtin_bit_cast(uint16_t, h);
-}
-__device__ __forceinline__ float dec_f16(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-
-// OCP E4M3: s eeee mmm, bias 7; exponent field 0 is subnormal (m * 2^-9); 0x7f / 0xff is NaN
-__device__ __forceinline__ uint8_t enc_e4m3(float x) {
-    const uint32_t u = __float_as_uint(x);
-    const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
-    const float a = fabsf(x);
-    if (!(a == a)) return sign | 0x7f;
-    if (a >= 464.0f) return sign | 0x7e;                 // saturate (448 and above round to 448)
-    if (a < 0.015625f) {                                 // below 2^-6: subnormal grid of 2^-9
-        const int m = (int)rintf(a * 512.0f);            // 0..8 (8 is the smallest normal, 0x08)
-        return sign | (uint8_t)m;
-    }
-    const uint32_t ua = __float_as_uint(a);
-    int e = (int)((ua >> 23) & 0xffu) - 127;
-    uint32_t mant = ua & 0x7fffffu;
-    const uint32_t r = mant + 0x7ffffu + ((mant >> 20) & 1u);   // RNE to 3 mantissa bits
-    uint32_t m3 = (r >> 20) & 7u;
-    if (r & 0x800000u) {
-        ++e;
-        m3 = 0;
-    }
-    const int E = e + 7;                                  // 1..15 here (a < 464)
-    return sign | (uint8_t)(E << 3) | (uint8_t)m3;
-}
-// decode by the hardware conversion (v_cvt_f32_fp8), which reads gfx950's FP8 bytes as OCP E4M3 like
-// the matrix instructions do; exact (every E4M3 value is a binary32 value)
-__device__ __forceinline__ float dec_e4m3(uint8_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
-
-template <int P> struct Codec;
-template <> struct Codec<LP_BF16> {
-    typedef uint16_t S;
-    static __device__ __forceinline__ S enc(float x) { return enc_bf16(x); }
-    static __device__ __forceinline__ float dec(S h) { return dec_bf16(h); }
-};
-template <> struct Codec<LP_F16> {
-    typedef uint16_t S;
-    static __device__ __forceinline__ S enc(float x) { return enc_f16(x); }
-    static __device__ __forceinline__ float dec(S h) { return dec_f16(h); }
-};
-template <> struct Codec<LP_FP8> {
-    typedef uint8_t S;
-    static __device__ __forceinline__ S enc(float x) { return enc_e4m3(x); }
-    static __device__ __forceinline__ float dec(S h) { return dec_e4m3(h); }
-};
-
-// eight consecutive elements: 16 bytes for 16-bit types, 8 bytes for FP8
-template <int P> struct Vec8 { typedef uint4 T; };
-template <> struct Vec8<LP_FP8> { typedef uint2 T; };
-
-template <int P>
-__device__ __forceinline__ f32x4 mfma32(const typename Vec8<P>::T& a, const typename Vec8<P>::T& b, f32x4 c);
-template <>
-__device__ __forceinline__ f32x4 mfma32<LP_BF16>(const uint4& a, const uint4& b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-}
-template <>
-__device__ __forceinline__ f32x4 mfma32<LP_F16>(const uint4& a, const uint4& b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
-                                                  0, 0);
-}
-template <>
-__device__ __forceinline__ f32x4 mfma32<LP_FP8>(const uint2& a, const uint2& b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0,
-                                                      0, 0);
-}
-
-__device__ __forceinline__ int64_t coloff(const Desc& d, int64_t c) {
-    return (c / d.seg) * d.segstride + (c % d.seg);
-}
-
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
-    if (G < 16) return b;
-    const int64_t q = G / 8, r = G % 8;
-    const int64_t x = b % 8, idx = b / 8;
-    return x * q + (x < r ? x : r) + idx;
-}
-
-// ---------------------------------------------------------------------------- GEMM
-// C(m, n) = alpha * sa[m] * sb[n % sb_mod] * sum_k A(m, k) B(k, n)
-// A: k-contiguous (desc rows m, columns k).  B: OB == KN -> desc rows k, columns n (n contiguous);
-// OB == MK (NK) -> desc rows n, columns k.  Output element type: float, or the 16-bit storage type
-// OUTP (LP_BF16 / LP_F16) of the sweep's intermediates.
-constexpr int LBM = 128, LBN = 128, LBK = 64;
-
-template <int P, int OB, int OUTP, bool VEC>
-__global__ __launch_bounds__(256, 2) void gemm_lp_kernel(LpGemmArgs g) {
-    typedef typename Codec<P>::S S;
-    typedef typename Vec8<P>::T V8;
-    constexpr int ES = (int)sizeof(S);
-    constexpr int PADK = 16 / ES;                  // 16-byte row padding
-    constexpr int LDK = LBK + PADK;                // LDS row stride in elements
-    __shared__ __attribute__((aligned(16))) S As[LBM * LDK];
-    __shared__ __attribute__((aligned(16))) S Bs[LBN * LDK];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-
-    const int64_t tilesM = (g.M + LBM - 1) / LBM;
-    const int64_t tilesN = (g.N + LBN - 1) / LBN;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t tm, tn;
-    if (g.lower_only) {
-        tm = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
-        while (tm * (tm + 1) / 2 > t) --tm;
-        tn = t - tm * (tm + 1) / 2;
-    } else {
-        tm = t % tilesM;
-        tn = t / tilesM;
-    }
-    if (tn >= tilesN || tm >= tilesM) return;
-    const int64_t m0 = tm * LBM, n0 = tn * LBN;
-    const int64_t kbeg = (int64_t)blockIdx.z * g.k_split;
-    const int64_t kend = (kbeg + g.k_split < g.K) ? kbeg + g.k_split : g.K;
-
-    const S* __restrict__ pa = (const S*)g.a.ptr;
-    const S* __restrict__ pb = (const S*)g.b.ptr;
-
-    // k-contiguous loader (A, and B when OB == MK): 128 rows x 64 k = 1024 vectors of 8,
-    // thread -> k-vector kv = tid % 8, rows tid / 8 + 32 u
-    const int kv = tid & 7;
-    const int rr = tid >> 3;
-    // n-contiguous loader (B when OB == KN): 64 k x 128 n as 4 x 8 blocks,
-    // thread -> k rows 4 * (tid % 16) .. +3, n columns 8 * (tid / 16) .. +7
-    const int bkq = tid & 15;
-    const int bng = tid >> 4;
-
-    V8 ra[4], rb[4];
-    S rbt[4][8];   // KN blocks: [k][n]
-
-    // k-contiguous operand column state: the 8-run at k = kcur (advanced by LBK per tile) sits at
-    // element offset kq * segstride + kr; one division at the start, increments afterwards
-    struct KCol {
-        int64_t kq, kr;
-    };
-    auto kcol_init = [&](const Desc& d, int64_t k) { return KCol{k / d.seg, k % d.seg}; };
-    auto kcol_next = [&](const Desc& d, KCol& c) {
-        c.kr += LBK;
-        while (c.kr >= d.seg) {
-            c.kr -= d.seg;
-            ++c.kq;
-        }
-    };
-    KCol ca = kcol_init(g.a, kbeg + 8 * kv);
-    KCol cb = kcol_init(g.b, kbeg + 8 * kv);
-    const int64_t bn_fix = (OB == KM && n0 + 8 * bng < g.N) ? coloff(g.b, n0 + 8 * bng) : 0;
-
-    auto load_kc = [&](const S* p, const Desc& d, const KCol& c, int64_t rows, int64_t row0, int64_t k0, V8* dst) {
-        const int64_t k = k0 + 8 * kv;
-        const int64_t co = c.kq * d.segstride + c.kr;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t row = row0 + rr + 32 * u;
-            V8 v;
-            if (VEC && row < rows && k + 8 <= kend) {
-                v = *(const V8*)(p + row * d.ld + co);
-            } else {
-                S e[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    e[j] = (row < rows && k + j < kend) ? p[row * d.ld + coloff(d, k + j)] : (S)0;
-                v = __builtin_bit_cast(V8, e);
-            }
-            dst[u] = v;
-        }
-    };
-    auto load_kn = [&](int64_t k0) {
-        const int64_t n = n0 + 8 * bng;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t k = k0 + 4 * bkq + q;
-            if (VEC && k < kend && n + 8 <= g.N) {
-                const V8 v = *(const V8*)(pb + k * g.b.ld + bn_fix);
-                const auto e = __builtin_bit_cast(S __attribute__((ext_vector_type(8))), v);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) rbt[q][j] = e[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    rbt[q][j] = (k < kend && n + j < g.N) ? pb[k * g.b.ld + coloff(g.b, n + j)] : (S)0;
-            }
-        }
-    };
-    auto load_tiles = [&](int64_t k0) {
-        load_kc(pa, g.a, ca, g.M, m0, k0, ra);
-        kcol_next(g.a, ca);
-        if (OB == KM) {
-            load_kn(k0);
-        } else {
-            load_kc(pb, g.b, cb, g.N, n0, k0, rb);
-            kcol_next(g.b, cb);
-        }
-    };
-    auto store_tiles = [&]() {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) *(V8*)(As + (rr + 32 * u) * LDK + 8 * kv) = ra[u];
-        if (OB == KM) {
-            // column n of the block -> Bs[n][4 bkq .. 4 bkq + 3]
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                S e[4] = {rbt[0][j], rbt[1][j], rbt[2][j], rbt[3][j]};
-                S* dst = Bs + (8 * bng + j) * LDK + 4 * bkq;
-                if constexpr (ES == 2) *(uint2*)dst = __builtin_bit_cast(uint2, e);
-                else *(uint32_t*)dst = __builtin_bit_cast(uint32_t, e);
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) *(V8*)(Bs + (rr + 32 * u) * LDK + 8 * kv) = rb[u];
-        }
-    };
-
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int fr = lane & 15;
-    const int fk = lane >> 4;          // which 8-wide k group of the 32-wide step
-    const int wbm = wm * 64, wbn = wn * 64;
-
-    if (kbeg < kend) {
-        load_tiles(kbeg);
-        store_tiles();
-        __syncthreads();
-        for (int64_t k0 = kbeg; k0 < kend; k0 += LBK) {
-            const bool more = (k0 + LBK) < kend;
-            if (more) load_tiles(k0 + LBK);
-#pragma unroll
-            for (int ks = 0; ks < LBK / 32; ++ks) {
-                V8 av[4], bv[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) av[i] = *(const V8*)(As + (wbm + i * 16 + fr) * LDK + ks * 32 + 8 * fk);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[j] = *(const V8*)(Bs + (wbn + j * 16 + fr) * LDK + ks * 32 + 8 * fk);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = mfma32<P>(av[i], bv[j], acc[i][j]);
-            }
-            __syncthreads();
-            if (more) {
-                store_tiles();
-                __syncthreads();
-            }
-        }
-    }
-
-    // epilogue: lane holds column (lane & 15), rows 4 * (lane >> 4) + v of each 16 x 16 tile
-    char* cbase = (char*)g.c.ptr;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t n = n0 + wbn + j * 16 + fr;
-        if (n >= g.N) continue;
-        if (g.c_valid > 0 && (n % g.c.seg) >= g.c_valid) continue;   // padding columns of a folded output
-        const int64_t co = coloff(g.c, n);
-        const float cs = (float)g.alpha * (g.sb ? g.sb[n % g.sb_mod] : 1.0f);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t m = m0 + wbm + i * 16 + 4 * fk + v;
-                if (m >= g.M) continue;
-                float val = acc[i][j][v] * cs;
-                if (g.sa) val *= g.sa[m];
-                const int64_t off = (int64_t)blockIdx.z * g.c_zstride + m * g.c.ld + co;
-                if (OUTP == LP_F32OUT) ((float*)cbase)[off] = val;
-                else if (OUTP == LP_BF16) ((uint16_t*)cbase)[off] = enc_bf16(val);
-                else ((uint16_t*)cbase)[off] = enc_f16(val);
-            }
-        }
-    }
-}
-
-template <int P, int OB, int OUTP>
-hipError_t launch_lp(const LpGemmArgs& g, bool vec, hipStream_t s) {
-    const int64_t tilesM = (g.M + LBM - 1) / LBM;
-    const int64_t tilesN = (g.N + LBN - 1) / LBN;
-    const int64_t tiles = g.lower_only ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
-    const int64_t splits = (g.K + g.k_split - 1) / g.k_split;
-    if (tiles == 0) return hipSuccess;
-    dim3 grid((unsigned)tiles, 1, (unsigned)(splits > 0 ? splits : 1));
-    if (vec) hipLaunchKernelGGL((gemm_lp_kernel<P, OB, OUTP, true>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm_lp_kernel<P, OB, OUTP, false>), grid, dim3(256), 0, s, g);
-    return hipGetLastError();
-}
-
-template <int P, int OB>
-hipError_t by_out(const LpGemmArgs& g, int outp, bool vec, hipStream_t s) {
-    if (outp == LP_F32OUT) return launch_lp<P, OB, LP_F32OUT>(g, vec, s);
-    if (outp == LP_BF16) return launch_lp<P, OB, LP_BF16>(g, vec, s);
-    if (outp == LP_F16) return launch_lp<P, OB, LP_F16>(g, vec, s);
-    return hipErrorInvalidValue;
-}
 
 // Vector (8-element) loads are legal when every 8-aligned run of a k-contiguous operand (or an
 // n-contiguous B) lies inside one segment and starts on a 16- (8-) byte boundary.
@@ -664,31 +341,14 @@ hipError_t gemm_lp(const LpGemmArgs& gin, int prec, Orient ob, int outp, hipStre
     LpGemmArgs g = gin;
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.k_split <= 0 || g.k_split > g.K) g.k_split = g.K > 0 ? g.K : 1;
-    if (g.k_split % LBK != 0 && g.k_split != g.K) return hipErrorInvalidValue;
+    if (g.k_split % kLpGemmK != 0 && g.k_split != g.K) return hipErrorInvalidValue;
     if (g.sb && g.sb_mod <= 0) return hipErrorInvalidValue;
     const int es = (prec == LP_FP8) ? 1 : 2;
     bool vec = desc_vec_ok(g.a, es) && desc_vec_ok(g.b, es);
-    if (prec == LP_BF16) {
-        return ob == KM ? by_out<LP_BF16, KM>(g, outp, vec, s) : by_out<LP_BF16, MK>(g, outp, vec, s);
-    }
-    if (prec == LP_F16) {
-        return ob == KM ? by_out<LP_F16, KM>(g, outp, vec, s) : by_out<LP_F16, MK>(g, outp, vec, s);
-    }
-    if (prec == LP_FP8) {
-        if (ob != KM) return hipErrorInvalidValue;   // FP8 only for the products over a tensor
-        if (outp == LP_BF16) return launch_lp<LP_FP8, KM, LP_BF16>(g, vec, s);
-        if (outp == LP_F32OUT) return launch_lp<LP_FP8, KM, LP_F32OUT>(g, vec, s);
-        return hipErrorInvalidValue;
-    }
+    if (prec == LP_BF16) return gemm_lp_bf16(g, ob, outp, vec, s);
+    if (prec == LP_F16) return gemm_lp_f16(g, ob, outp, vec, s);
+    if (prec == LP_FP8) return gemm_lp_fp8(g, ob, outp, vec, s);
     return hipErrorInvalidValue;
-}
-
-int64_t gemm_lp_blocks(const LpGemmArgs& g) {
-    const int64_t tilesM = (g.M + LBM - 1) / LBM;
-    const int64_t tilesN = (g.N + LBN - 1) / LBN;
-    const int64_t tiles = g.lower_only ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
-    const int64_t ks = (g.k_split <= 0 || g.k_split > g.K) ? g.K : g.k_split;
-    return tiles * ((g.K + ks - 1) / (ks > 0 ? ks : 1));
 }
 
 static unsigned grid_for(int64_t n) {

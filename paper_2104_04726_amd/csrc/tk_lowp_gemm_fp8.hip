@@ -1,0 +1,11 @@
+// FP8 instantiation of the reduced-precision GEMM (kernel and tiling in tk_lowp_gemm.h).
+#include "tk_lowp_gemm.h"
+
+namespace tk {
+
+hipError_t gemm_lp_fp8(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s) {
+    if (ob != KM) return hipErrorInvalidValue;   // FP8 only for the products over a tensor
+    return by_out<LP_FP8, KM>(g, outp, vec, s);
+}
+
+}  // namespace tk

@@ -7,7 +7,9 @@
 // fastest is kept; otherwise the heuristic choice is kept.  Every later call with the same key reuses
 // it, so within a process a shape's results do not depend on which calls ran before or beside it.
 // Candidates of one key must leave identical results or results of one fixed reduction order each,
-// and their outputs must be idempotent (stores, not accumulations).
+// and their outputs must be idempotent (stores, not accumulations).  tune_force overrides the choice
+// of one operation process-wide (for comparing candidates) without touching the table.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -30,6 +32,8 @@ struct Entry {
 std::mutex g_mu;
 std::map<Key, Entry> g_table;
 thread_local bool t_enabled = false;
+constexpr int kMaxOp = 4;
+std::atomic<int> g_force[kMaxOp] = {-1, -1, -1, -1};
 
 }  // namespace
 
@@ -39,6 +43,10 @@ bool tune_enabled() { return t_enabled; }
 int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStream_t s,
                 const std::function<hipError_t(int)>& launch, hipError_t* err) {
     *err = hipSuccess;
+    if (op > 0 && op < kMaxOp) {
+        const int f = g_force[op].load(std::memory_order_relaxed);
+        if (f >= 0) return f < ncand ? f : ncand - 1;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     const Key key{op, dev, shape[0], shape[1], shape[2], shape[3], shape[4]};
@@ -111,6 +119,12 @@ std::string tune_dump() {
 void tune_clear() {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
+}
+
+bool tune_force(int op, int choice) {
+    if (op <= 0 || op >= kMaxOp) return false;
+    g_force[op].store(choice < 0 ? -1 : choice, std::memory_order_relaxed);
+    return true;
 }
 
 size_t tune_size() {

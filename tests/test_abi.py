@@ -63,6 +63,18 @@ def test_workspace_size_and_status_strings():
     assert lib.tucker_last_error(None) == b""
 
 
+def test_autotune_host_controls():
+    # the table and the per-operation override are host state: no device needed
+    assert isinstance(tk.autotune_table(), str)
+    tk.autotune_clear()
+    for op in (1, 2, 3):
+        tk.autotune_force(op, 1)
+        tk.autotune_force(op, -1)
+    for bad in (0, 4, -1):
+        with pytest.raises(tk.TuckerError):
+            tk.autotune_force(bad, 0)
+
+
 def test_null_context_and_arguments_are_rejected():
     lib = _lib.lib()
     dims = _lib.i64((4, 3, 2))

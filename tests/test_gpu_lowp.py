@@ -182,3 +182,48 @@ def test_lowp_unsupported_shape():
         assert e.value.code == 5
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lowp_tile_variants_bit_identical(ctx, prec):
+    """The LDS stagings the autotuner chooses between (operation 3) leave every output element's sum
+    and its order unchanged: each candidate's products and Grams equal the first's bit for bit, on
+    shapes with interior tiles (unchecked loads) and ragged edge tiles."""
+    import paper_2104_04726_amd as tk
+    rng = np.random.default_rng(23)
+    cases = [((520, 96, 3, 14), 0, 300), ((40, 530, 42), 1, 270), ((200, 300, 3, 14), 1, 130)]
+    grams = [((300, 200), 0), ((2, 390, 42), 1)] if prec != "fp8" else []
+    data = [(_dev((rng.standard_normal(s) + 0.2).astype(np.float32)), m,
+             _dev(rng.standard_normal((s[m], r)).astype(np.float32))) for s, m, r in cases]
+    gdata = [(_dev((rng.standard_normal(s) + 0.5).astype(np.float32)), m) for s, m in grams]
+    outs = []
+    try:
+        for c in range(2):
+            tk.autotune_force(3, c)
+            _say(f"{prec}: tile variant {c}")
+            outs.append([ctx.ttm_lowp(x, m, u, prec).cpu().numpy() for x, m, u in data] +
+                        [ctx.gram_lowp(x, m, prec).cpu().numpy() for x, m in gdata])
+    finally:
+        tk.autotune_force(3, -1)
+    for c in range(1, 2):
+        for a, b in zip(outs[0], outs[c]):
+            assert a.shape == b.shape and np.array_equal(a, b), (prec, c)
+
+
+def test_lowp_decomposition_same_for_every_tile_variant():
+    import paper_2104_04726_amd as tk
+    c = STACK_CONFIGS["stack_mini"]
+    x = _dev(make_stereo_stack(c["H"], c["W"], c["E"], c["colorspace"], c["seed"]))
+    res = []
+    try:
+        for v in (0, 1):
+            tk.autotune_force(3, v)
+            with tk.Context(0, precision="bf16", refine_sweeps=1) as cx:
+                r = cx.decompose(x, c["ranks"], 3)
+            res.append((r.fit, r.core.cpu().numpy(), [u.cpu().numpy() for u in r.factors]))
+    finally:
+        tk.autotune_force(3, -1)
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    for a, b in zip(res[0][2], res[1][2]):
+        assert np.array_equal(a, b)
