@@ -49,7 +49,7 @@ constexpr size_t kNoAllocAlign = 256;
 constexpr size_t align_up(size_t v) { return (v + kNoAllocAlign - 1) / kNoAllocAlign * kNoAllocAlign; }
 constexpr size_t kNoAllocW = 0;                                                     // n x n doubles
 constexpr size_t kNoAllocCtr = align_up(kNoAllocW + sizeof(double) * kNoAllocMaxN * kNoAllocMaxN);
-constexpr size_t kNoAllocCtrInts = 2 + 2 * ((kNoAllocMaxN + 63) / 64) * ((kNoAllocMaxN + 63) / 64);
+constexpr size_t kNoAllocCtrInts = 2 + 2 * ((kNoAllocMaxN + kCholTile - 1) / kCholTile) * ((kNoAllocMaxN + kCholTile - 1) / kCholTile);
 constexpr size_t kNoAllocDsc = align_up(kNoAllocCtr + sizeof(int) * kNoAllocCtrInts);     // n doubles
 constexpr size_t kNoAllocShifts = align_up(kNoAllocDsc + sizeof(double) * kNoAllocMaxN);  // 8 ints
 constexpr size_t kNoAllocBytes = align_up(kNoAllocShifts + 8 * sizeof(int));

@@ -139,6 +139,9 @@ hipError_t fit_from_resid(const double* nx2, const double* r2, double* fit, hipS
 // result is garbage and the caller must report an error.
 // run_if (nullable): every kernel of the call returns at once when *run_if == 0.
 constexpr int kWaitTimeoutSlot = 5;
+// tile edge of the Cholesky task graph (32: a shorter critical path per block column than 64 on
+// gfx950, whose FP64 matrix rate makes the 64 x 64 tile products the slow link)
+constexpr int kCholTile = 32;
 hipError_t chol_inv_scaled(double* W, int64_t n, bool scale, double shift, double* Tout, int* counters,
                            double* dsc, int* shifts, hipStream_t s, const int* run_if = nullptr,
                            long long max_spin = 0);

@@ -2,7 +2,8 @@
 //
 // chol_inv_scaled: W~ = D^-1 W D^-1 (D = sqrt(diag W)) is factored W~ = L L^T and T = L^-1 D^-1 is
 //   produced, so that Q = Z T^T has orthonormal columns when W = Z^T Z (one CholeskyQR pass).
-//   The n x n problem is split into 64 x 64 tiles and run as one launch of a tiled task graph:
+//   The n x n problem is split into TB x TB tiles (TB = kCholTile) and run as one launch of a tiled
+//   task graph:
 //   factor tasks in column-major order, then inverse tasks (i,j), i > j.  The diagonal task (j,j)
 //   also forms the sub-diagonal tile L(j,j-1) as soon as the inverse of L(j-1,j-1) is published
 //   and applies its update from LDS, so the critical path crosses one flag per column.
@@ -23,10 +24,7 @@
 namespace tk {
 namespace {
 
-#ifndef TK_CHOL_TB
-#define TK_CHOL_TB 64
-#endif
-constexpr int TB = TK_CHOL_TB;
+constexpr int TB = kCholTile;
 constexpr int TS = TB + 1;                  // padded LDS row stride
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr long long kMaxSpin = 1ll << 24;   // default bound of a wait (x ~64 cycles of sleep each)
@@ -71,7 +69,7 @@ __device__ __forceinline__ void stores_done() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__device__ void wait_flags(int* f1, int* f2, int* err, long long max_spin) {
+__device__ __attribute__((always_inline)) void wait_flags(int* f1, int* f2, int* err, long long max_spin) {
     if (threadIdx.x == 0) {
         long long it = 0;
         bool ready;
@@ -85,7 +83,7 @@ __device__ void wait_flags(int* f1, int* f2, int* err, long long max_spin) {
     __syncthreads();
 }
 
-__device__ void release_flag(int* f) {
+__device__ __attribute__((always_inline)) void release_flag(int* f) {
     stores_done();
     __syncthreads();
     if (threadIdx.x == 0) st_flag(f, 1);
@@ -96,7 +94,7 @@ __device__ void release_flag(int* f) {
 // issues all of its TB*TB/256 coherent loads before the first use, so their latencies overlap.
 constexpr int kTileVals = TB * TB / 256;
 
-__device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dr,
+__device__ __attribute__((always_inline)) void load_tile(const double* M, int64_t n, int ti, int tj, double* t, const double* dr,
                           const double* dc, bool pad_diag, double shift = 0.0) {
     double v[kTileVals];
 #pragma unroll
@@ -124,7 +122,7 @@ __device__ void load_tile(const double* M, int64_t n, int ti, int tj, double* t,
     }
 }
 
-__device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t) {
+__device__ __attribute__((always_inline)) void store_tile(double* M, int64_t n, int ti, int tj, const double* t) {
 #pragma unroll
     for (int u = 0; u < kTileVals; ++u) {
         const int e = threadIdx.x + 256 * u;
@@ -135,42 +133,42 @@ __device__ void store_tile(double* M, int64_t n, int ti, int tj, const double* t
 }
 
 // C = beta*C + alpha * A * op(B), op(B) = B^T when transB, on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64).  256 threads = 4 waves; wave w owns the 32 x 32 quadrant at rows
-// 32 (w & 1), columns 32 (w >> 1) as 2 x 2 tiles of 16 x 16.  Fragment layouts: A lane l holds
+// (v_mfma_f64_16x16x4f64).  256 threads = 4 waves; wave w owns the TB/2 x TB/2 quadrant at rows
+// TB/2 (w & 1), columns TB/2 (w >> 1) as 16 x 16 tiles.  Fragment layouts: A lane l holds
 // (row l % 16, k l / 16), B lane l holds (k l / 16, column l % 16), the result lane l holds
 // column l % 16 and rows l / 16 + 4 v.  C may alias A or B (results are written after a barrier).
-__device__ void tile_gemm(double* C, const double* A, const double* B, bool transB, double alpha,
-                          double beta) {
-    static_assert(TB == 64, "tile_gemm assumes 64 x 64 tiles and 256 threads");
+__device__ __attribute__((always_inline)) void tile_gemm(double* C, const double* A, const double* B, bool transB,
+                                                         double alpha, double beta) {
+    constexpr int H = TB / 2, NT = TB / 32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = 32 * (wave & 1), col0 = 32 * (wave >> 1);
+    const int row0 = H * (wave & 1), col0 = H * (wave >> 1);
     const int fr = lane & 15, fk = lane >> 4;
-    f64x4_t acc[2][2];
+    f64x4_t acc[NT][NT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < NT; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int k0 = 0; k0 < TB; k0 += 4) {
         const int k = k0 + fk;
-        double av[2], bv[2];
+        double av[NT], bv[NT];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) av[i] = A[(row0 + 16 * i + fr) * TS + k];
+        for (int i = 0; i < NT; ++i) av[i] = A[(row0 + 16 * i + fr) * TS + k];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NT; ++j) {
             const int c = col0 + 16 * j + fr;
             bv[j] = transB ? B[c * TS + k] : B[k * TS + c];
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NT; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();   // C may alias A or B
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NT; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double* d = &C[(row0 + 16 * i + fk + 4 * v) * TS + col0 + 16 * j + fr];
@@ -179,11 +177,11 @@ __device__ void tile_gemm(double* C, const double* A, const double* B, bool tran
     __syncthreads();
 }
 
-// ---- 64 x 64 tile factorisation and inversion, blocked by 16: the sequential parts are 16 x 16
+// ---- TB x TB tile factorisation and inversion, blocked by 16: the sequential parts are 16 x 16
 // problems solved inside one wave's registers (row r in lane r, column entries broadcast across
 // lanes, no barriers); the rest is parallel over the workgroup with a barrier per phase.
 constexpr int SB = 16;   // inner block
-static_assert(TB == 64, "blocked tile kernels assume 64 x 64 tiles");
+static_assert(TB == 32 || TB == 64, "the tile kernels assume 32 x 32 or 64 x 64 tiles and 256 threads");
 
 __device__ __forceinline__ double safe_pivot(double d) { return (d > 1e-13) ? d : 1e-13; }
 
@@ -251,7 +249,7 @@ __device__ __forceinline__ void ldl_finish(double (&a)[SB], double (&x)[SB], dou
 // One wave (all 64 lanes active): Cholesky of the 16 x 16 diagonal block at (o, o) of A (LDS, row
 // stride TS), in place (lower L, upper zeroed), and L^-1 into X (LDS, row stride ldx, zeros above
 // the diagonal).  Pivots <= 1e-13 are replaced by 1e-13 and counted in *shifts.
-__device__ void wave_potrf16(double* A, int o, double* X, int ldx, int* shifts) {
+__device__ __attribute__((always_inline)) void wave_potrf16(double* A, int o, double* X, int ldx, int* shifts) {
     const int lane = threadIdx.x & 63, r = lane & 15;
     double a[SB], x[SB];
 #pragma unroll
@@ -275,12 +273,12 @@ __device__ void wave_potrf16(double* A, int o, double* X, int ldx, int* shifts) 
     if (lane == 0 && bad) atomicAdd(shifts, bad);
 }
 
-// In-LDS Cholesky of the 64 x 64 tile A (lower; upper zeroed); the inverses of its four diagonal
+// In-LDS Cholesky of the TB x TB tile A (lower; upper zeroed); the inverses of its TB/16 diagonal
 // 16 x 16 blocks go to the diagonal blocks of X (row stride TS).  Right-looking over the 16-wide
 // block columns: wave 0 factors and inverts the diagonal block; the block column below,
 // L_ib = A_ib L_bb^-T, and the trailing update A_ij -= L_ib L_jb^T (i >= j, 16 x 16 tiles) run on
 // the FP64 matrix cores, one 16 x 16 tile per wave.
-__device__ void tile_potrf(double* A, double* X, int* shifts) {
+__device__ __attribute__((always_inline)) void tile_potrf(double* A, double* X, int* shifts) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fk = lane >> 4;
     for (int b = 0; b < TB / SB; ++b) {
@@ -330,10 +328,10 @@ __device__ void tile_potrf(double* A, double* X, int* shifts) {
     __syncthreads();
 }
 
-// Inverse of the lower-triangular 64 x 64 tile L (LDS) into X (LDS), given the inverses of the
+// Inverse of the lower-triangular TB x TB tile L (LDS) into X (LDS), given the inverses of the
 // diagonal 16 x 16 blocks in X and zeros above them: block forward substitution over the block
 // rows, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj, on the FP64 matrix cores.
-__device__ void tile_trtri(const double* L, double* X) {
+__device__ __attribute__((always_inline)) void tile_trtri(const double* L, double* X) {
     __shared__ double Tm[3 * SB * SB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -429,14 +427,14 @@ __global__ __launch_bounds__(256) void chol_graph(CholArgs a) {
                 tile_gemm(At, Bt, Bt, true, -1.0, 1.0);
                 tile_gemm(Ct, Bt, Dt, true, -1.0, 1.0);
             }
-            // L_j,j-1 = A_j,j-1 Linv_j-1^T, published at once; then A_jj -= L_j,j-1 L_j,j-1^T from LDS
+            // L_j,j-1 = A_j,j-1 Linv_j-1^T; A_jj -= L_j,j-1 L_j,j-1^T from LDS while its stores drain
             wait_flags(fI(j - 1, j - 1), nullptr, a.err, a.max_spin);
             load_tile(a.Tout, a.n, j - 1, j - 1, Bt, nullptr, nullptr, false);
             __syncthreads();
             tile_gemm(Dt, Ct, Bt, true, 1.0, 0.0);
             store_tile(a.W, a.n, j, j - 1, Dt);
+            tile_gemm(At, Dt, Dt, true, -1.0, 1.0);   // overlaps the stores of L_j,j-1
             release_flag(fL(j, j - 1));
-            tile_gemm(At, Dt, Dt, true, -1.0, 1.0);
         } else {
             for (int k = 0; k < j; ++k) {
                 wait_flags(fL(i, k), fL(j, k), a.err, a.max_spin);
