@@ -570,52 +570,54 @@ __global__ __launch_bounds__(256) void small_gram_kernel(const float* __restrict
 }
 
 // ---------------------------------------------------------------- split-K Gram reduction
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const float* __restrict__ P, int nsplit,
-                                                          int64_t n, int64_t zstride,
-                                                          float* __restrict__ S32,
+// S(i, j) = S(j, i) = sum_z P_z(i, j) for i >= j, summed in split order in FP64 (the partials hold the
+// lower triangle of n x n row-major Grams, zstride apart).  One 32 x 32 lower tile (I >= J) per block:
+// the partials are read once and row-wise, the tile is written as it is and, through LDS, transposed,
+// so that every load and store is coalesced.
+template <typename TP>
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const TP* __restrict__ P, int nsplit, int64_t n,
+                                                          int64_t zstride, float* __restrict__ S32,
                                                           double* __restrict__ S64) {
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / n, j = e % n;
-        const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
-        // loads issued four at a time, summed in split order (same result as a plain loop)
+    __shared__ double tile[32][33];
+    const int64_t b = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int64_t J = b - I * (I + 1) / 2;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        const int64_t i = 32 * I + r, j = 32 * J + tx;
         double s = 0.0;
-        int z = 0;
-        for (; z + 4 <= nsplit; z += 4) {
-            const float a0 = P[(int64_t)z * zstride + src], a1 = P[(int64_t)(z + 1) * zstride + src];
-            const float a2 = P[(int64_t)(z + 2) * zstride + src], a3 = P[(int64_t)(z + 3) * zstride + src];
-            s += (double)a0;
-            s += (double)a1;
-            s += (double)a2;
-            s += (double)a3;
+        if (i < n && j < n && (I != J || r >= tx)) {
+            const int64_t src = i * n + j;
+            int z = 0;
+            for (; z + 4 <= nsplit; z += 4) {
+                const TP a0 = P[(int64_t)z * zstride + src], a1 = P[(int64_t)(z + 1) * zstride + src];
+                const TP a2 = P[(int64_t)(z + 2) * zstride + src], a3 = P[(int64_t)(z + 3) * zstride + src];
+                s += (double)a0;
+                s += (double)a1;
+                s += (double)a2;
+                s += (double)a3;
+            }
+            for (; z < nsplit; ++z) s += (double)P[(int64_t)z * zstride + src];
+            if (S32) S32[src] = (float)s;
+            if (S64) S64[src] = s;
         }
-        for (; z < nsplit; ++z) s += (double)P[(int64_t)z * zstride + src];
-        if (S32) S32[e] = (float)s;
-        if (S64) S64[e] = s;
+        tile[r][tx] = s;
     }
-}
-
-__global__ __launch_bounds__(256) void gram_reduce64_kernel(const double* __restrict__ P, int nsplit,
-                                                            int64_t n, int64_t zstride,
-                                                            double* __restrict__ S64) {
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / n, j = e % n;
-        const int64_t src = (i >= j) ? (i * n + j) : (j * n + i);
-        double s = 0.0;
-        int z = 0;
-        for (; z + 4 <= nsplit; z += 4) {
-            const double a0 = P[(int64_t)z * zstride + src], a1 = P[(int64_t)(z + 1) * zstride + src];
-            const double a2 = P[(int64_t)(z + 2) * zstride + src], a3 = P[(int64_t)(z + 3) * zstride + src];
-            s += a0;
-            s += a1;
-            s += a2;
-            s += a3;
+    __syncthreads();
+    // the mirror: S(32 J + r, 32 I + c) = tile[c][r], strictly above the diagonal
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        const int64_t i = 32 * J + r, j = 32 * I + tx;
+        if (i < n && j < n && (I != J || tx > r)) {
+            const double v = tile[tx][r];
+            if (S32) S32[i * n + j] = (float)v;
+            if (S64) S64[i * n + j] = v;
         }
-        for (; z < nsplit; ++z) s += P[(int64_t)z * zstride + src];
-        S64[e] = s;
     }
 }
 
@@ -813,16 +815,23 @@ hipError_t small_gram(const float* in, int64_t A, int64_t sdim, int64_t B, doubl
     return hipGetLastError();
 }
 
+static unsigned gram_reduce_blocks(int64_t n) {
+    const int64_t t = (n + 31) / 32;
+    return (unsigned)(t * (t + 1) / 2);
+}
+
 hipError_t gram_reduce(const float* P, int nsplit, int64_t n, int64_t zstride, float* S32, double* S64,
                        hipStream_t s) {
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for(n * n, 4096)), dim3(256), 0, s, P, nsplit, n, zstride,
-                       S32, S64);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(gram_reduce_blocks(n)), dim3(256), 0, s, P, nsplit, n,
+                       zstride, S32, S64);
     return hipGetLastError();
 }
 
 hipError_t gram_reduce64(const double* P, int nsplit, int64_t n, int64_t zstride, double* S64, hipStream_t s) {
-    hipLaunchKernelGGL(gram_reduce64_kernel, dim3(grid_for(n * n, 4096)), dim3(256), 0, s, P, nsplit, n, zstride,
-                       S64);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(gram_reduce_blocks(n)), dim3(256), 0, s, P, nsplit, n,
+                       zstride, nullptr, S64);
     return hipGetLastError();
 }
 
