@@ -246,6 +246,20 @@ def serve(args):
         sat_sum = summary(res_sat, wall_sat)
         log(f"  {sat_sum}")
         st = srv.stats()
+    # grouped burst: requests of one class submitted at once, run with and without grouped launches
+    # of their reduced-precision products (groups form from consecutive requests of one class)
+    bH, bW = sizes[len(sizes) // 2]
+    burst = [dict(H=bH, W=bW, E=5, ranks=(bH // 4, bW // 4, 3, 9), t_arrive=0.0)] * args.burst
+    burst_sum = {}
+    for key, grouped, graphs in (("alone", False, not args.no_serve_graphs), ("alone_no_graphs", False, False),
+                                 ("grouped", True, False)):
+        with tk.Server(0, slots=args.slots, use_graphs=graphs, group_requests=4 if grouped else 0) as srv:
+            run(srv, burst[:args.slots], open_loop=False)
+            res_b, wall_b = run(srv, burst, open_loop=False)
+            bst = srv.stats()
+        burst_sum[key] = dict(summary(res_b, wall_b), grouped_requests=bst["grouped_requests"],
+                              group_launches=bst["group_launches"], grouped_products=bst["grouped_products"])
+        log(f"burst {key}: {burst_sum[key]}")
     # baseline: the same requests one after another in plain FP32 (10 sweeps), on a stratified
     # sample of one request per (resolution, exposures) cell
     ctx = tk.Context(0)
@@ -276,6 +290,9 @@ def serve(args):
                    "peak_admitted_bytes": st["peak_admitted_bytes"], "peak_running": st["peak_running"]},
         "open_loop": open_sum,
         "saturated": sat_sum,
+        "grouped_burst": dict(burst_sum, workload=f"{args.burst} requests {bH}x{bW}x3x10 at once, ranks "
+                                                  f"({bH // 4}, {bW // 4}, 3, 9), {iters} {args.serve_precision} sweeps"),
+        "group_stats": {"grouped_requests": st["grouped_requests"], "group_launches": st["group_launches"]},
         "sequential_fp32_baseline": {"decomp_per_s": round(seq_rate, 3),
                                      "sample": f"{len(times)} requests, one per (resolution, E) cell, plain FP32, "
                                                f"{iters} sweeps, one at a time"},
@@ -317,12 +334,15 @@ def main():
                     help="pairwise-perturbation sweeps once the factors settle to this subspace distance (0: off)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="operand precision of the sweeps (reduced precision adds one FP32 refinement sweep)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="launch choices from the built-in heuristics instead of measuring them during the warm-up")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each sweep as a HIP graph on a side stream (no per-stage timers)")
     ap.add_argument("--serve", action="store_true", help="run the served-execution benchmark instead")
     ap.add_argument("--no-serve-graphs", action="store_true", help="serving slots launch kernel by kernel")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--saturated", type=int, default=128)
+    ap.add_argument("--burst", type=int, default=32, help="requests of one class in the grouped-burst comparison")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp16", "fp8"])
     ap.add_argument("--copy-probe", action="store_true",
@@ -355,15 +375,18 @@ def main():
     if args.graphs:
         side = torch.cuda.Stream()
         ctx = tk.Context(0, stream=side, timing=False, precision=args.precision, refine_sweeps=1,
-                         init_iters=args.init_iters, use_graphs=True, start=args.start, pp_tol=args.pp_tol)
+                         init_iters=args.init_iters, use_graphs=True, start=args.start, pp_tol=args.pp_tol,
+                         autotune=not args.no_autotune)
     else:
         ctx = tk.Context(0, timing=True, precision=args.precision, refine_sweeps=1, init_iters=args.init_iters,
-                         start=args.start, pp_tol=args.pp_tol)
+                         start=args.start, pp_tol=args.pp_tol, autotune=not args.no_autotune)
     for i in range(args.warmup):
         r = ctx.decompose(x, ranks, sweeps)
         log(f"warmup {i}: fit {r.fit:.8f} sweeps {r.sweeps} init {r.stats['init_ms']:.2f} ms "
             f"sweeps {r.stats['sweeps_ms']:.2f} ms")
     torch.cuda.synchronize()
+    if not args.no_autotune:
+        log("autotuner choices:\n" + tk.autotune_table().rstrip())
     stage_tot = {}
     init_ms = sweeps_ms = 0.0
     t0 = time.perf_counter()
@@ -424,7 +447,7 @@ def main():
                    "precision": args.precision,
                    "sweeps_per_step": sweeps, "fit": round(r.fit, 9),
                    "orth_second_passes": r.stats.get("orth_second_passes"),
-                   "pp_tol": args.pp_tol, "pp_sweeps": r.stats.get("pp_sweeps"),
+                   "pp_tol": args.pp_tol, "pp_sweeps": r.stats.get("pp_sweeps"), "autotune": not args.no_autotune,
                    "init_ms": round(init_ms / args.steps, 3), "sweeps_ms": round(sweeps_ms / args.steps, 3)},
         "roofline": roof,
         "stages": stages,

@@ -349,6 +349,15 @@ typedef struct {
     uint64_t seed;
     int use_graphs;              /* 1: slots replay each request's sweep as a HIP graph       */
     int autotune;                /* as in tucker_options (default 1)                          */
+    int group_requests;          /* largest number of requests run as one group (0 or 1: no
+                                    grouping, the default; at most 12).  Consecutive queued
+                                    requests of one shape class (dims, ranks, reduced precision,
+                                    max_iters, refine_sweeps, tol = 0) that fit in the budget
+                                    are admitted together by one slot, each member on a context
+                                    of its own, and their reduced-precision sweep products run
+                                    as grouped persistent launches over all members' tiles (their
+                                    sweeps are then not replayed as graphs).  Results are bit for
+                                    bit those of the requests run alone.                        */
 } tucker_server_options;
 
 typedef struct {
@@ -381,10 +390,13 @@ typedef struct {
     size_t budget_bytes;
     size_t peak_admitted_bytes;  /* largest sum of admitted footprints seen                   */
     int peak_running;            /* largest number of requests running at once               */
+    int64_t grouped_requests;    /* requests that ran as members of a group                  */
+    int64_t group_launches;      /* grouped persistent launches those groups made             */
+    int64_t grouped_products;    /* products those launches computed                          */
 } tucker_server_stats;
 
 /* Defaults: device 0, 4 slots, budget 0 (90% of free memory), inner_iters 1, init_iters 20,
- * use_graphs 1. */
+ * use_graphs 1, autotune 1, group_requests 0. */
 void tucker_default_server_options(tucker_server_options* o);
 /* ERR_DEVICE without a usable GPU; ERR_INVALID_ARG for bad options. */
 tucker_status tucker_server_create(const tucker_server_options* opts, tucker_server** out);

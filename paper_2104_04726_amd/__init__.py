@@ -397,17 +397,22 @@ def _host_ptr(a):
 
 class Server:
     """Request loop of the library (tucker_server_*): admission by HBM budget, `slots` requests
-    in flight on their own streams.  submit() copies nothing and returns at once; the host
-    tensor must stay alive until wait() returns its result."""
+    in flight on their own streams.  With group_requests > 1, consecutive requests of one shape class
+    (up to group_requests of them) are admitted together and share grouped persistent launches of
+    their reduced-precision products.
+    submit() copies nothing and returns at once; the host tensor must stay alive until wait()
+    returns its result."""
 
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget_bytes: int = 0, inner_iters: int = 1,
-                 init_iters: int = 20, seed: int = 0x5EED, use_graphs: bool = True, autotune: bool = True):
+                 init_iters: int = 20, seed: int = 0x5EED, use_graphs: bool = True, autotune: bool = True,
+                 group_requests: int = 0):
         o = _lib.ServerOptions()
         _lib.lib().tucker_default_server_options(C.byref(o))
         o.device, o.slots, o.hbm_budget_bytes = int(device), int(slots), int(hbm_budget_bytes)
         o.inner_iters, o.init_iters, o.seed = int(inner_iters), int(init_iters), int(seed)
         o.use_graphs = 1 if use_graphs else 0
         o.autotune = 1 if autotune else 0
+        o.group_requests = int(group_requests)
         h = C.c_void_p()
         _check(_lib.lib().tucker_server_create(C.byref(o), C.byref(h)))
         self._h = h

@@ -74,6 +74,7 @@ class ServerOptions(C.Structure):
         ("seed", C.c_uint64),
         ("use_graphs", C.c_int),
         ("autotune", C.c_int),
+        ("group_requests", C.c_int),
     ]
 
 
@@ -117,6 +118,9 @@ class ServerStats(C.Structure):
         ("budget_bytes", C.c_size_t),
         ("peak_admitted_bytes", C.c_size_t),
         ("peak_running", C.c_int),
+        ("grouped_requests", C.c_int64),
+        ("group_launches", C.c_int64),
+        ("grouped_products", C.c_int64),
     ]
 
 

@@ -1397,6 +1397,13 @@ void lp_factor(Run& r, int n, int prec, void* Ut, float* scale) {
     TK_HIP(factor_lowp(p.U32[n], p.s[n], p.R[n], sp, prec, scale, Ut, r.st));
 }
 
+// a reduced-precision product of a sweep: through the calling thread's lock-step group when it has
+// one (served requests of one shape), else launched alone
+hipError_t lp_launch(const LpGemmArgs& g, int prec, Orient ob, int outp, hipStream_t st) {
+    if (LpGrouper* G = lp_group_current()) return G->gemm(g, prec, ob, outp, st);
+    return gemm_lp(g, prec, ob, outp, st);
+}
+
 // mode product out = B x U^T on the matrix cores: A = Ut (M = R rows, K = s), B an n-contiguous view
 void lp_ttm(Run& r, int prec, const void* Ut, int64_t R, int64_t K, Desc b, int64_t N, Desc c, int outp,
             const float* sa = nullptr, const float* sb = nullptr, int64_t sb_mod = 0, int64_t c_valid = 0) {
@@ -1413,7 +1420,7 @@ void lp_ttm(Run& r, int prec, const void* Ut, int64_t R, int64_t K, Desc b, int6
     g.sa = sa;
     g.sb = sb;
     g.sb_mod = sb_mod;
-    TK_HIP(gemm_lp(g, prec, KM, outp, r.st));
+    TK_HIP(lp_launch(g, prec, KM, outp, r.st));
 }
 
 // S64 = Y Y^T for a k-contiguous view Y (s rows, K columns): FP32 partials over K splits, summed in FP64
@@ -1434,7 +1441,7 @@ void lp_gram(Run& r, Desc y, int64_t srows, int64_t K, int stage) {
     g.c_zstride = srows * srows;
     {
         StageTimer t(r, stage);
-        TK_HIP(gemm_lp(g, p.ip, MK, LP_F32OUT, r.st));
+        TK_HIP(lp_launch(g, p.ip, MK, LP_F32OUT, r.st));
     }
     StageTimer t(r, stage >= 0 ? TUCKER_STAGE_REDUCE : -1);
     TK_HIP(gram_reduce(p.Pf, nsplit, srows, srows * srows, nullptr, p.S64, r.st));
@@ -2658,6 +2665,8 @@ void tk_ctx_release_workspace(tucker_ctx* ctx) {
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
 }
+
+void tk_ctx_set_graphs(tucker_ctx* ctx, bool on) { ctx->opt.use_graphs = on ? 1 : 0; }
 
 void tk_ctx_set_run_options(tucker_ctx* ctx, tucker_precision precision, int refine_sweeps) {
     ctx->opt.precision = precision;

@@ -1,5 +1,9 @@
 // Reduced-precision (BF16 / FP16 / FP8-e4m3) contraction kernels of the HOOI sweep.
 #pragma once
+#include <condition_variable>
+#include <mutex>
+#include <vector>
+
 #include "tk_common.h"
 
 namespace tk {
@@ -24,6 +28,70 @@ struct LpGemmArgs {
 // (ob == KM: desc rows k, columns n) or k-contiguous (ob == MK: desc rows n, columns k).
 // Operands in the storage type prec; output float (outp == LP_F32OUT) or BF16/FP16.
 // FP8 is provided for ob == KM with a BF16 output (the full-tensor product).
+// A group of products of one kind (storage type, B orientation, output type), launched as one
+// persistent grid over their work items (tiles x k splits); ctr: two device counters that are zero on
+// entry and zero again when the launch has finished (one pair per stream that launches groups).
+constexpr int kLpGroupMax = 12;
+struct LpGroupArgs {
+    LpGemmArgs p[kLpGroupMax];
+    int64_t start[kLpGroupMax + 1];   // prefix sums of the products' work items
+    int n;
+    unsigned* ctr;
+};
+// work items of one product in a grouped launch: 128 x 128 output tiles (lower-triangle tiles of a
+// Gram) times k splits
+inline int64_t lp_work_items(const LpGemmArgs& g) {
+    const int64_t tilesM = (g.M + 127) / 128;
+    const int64_t tilesN = (g.N + 127) / 128;
+    const int64_t tiles = g.lower_only ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
+    return tiles * ((g.K + g.k_split - 1) / g.k_split);
+}
+// C_i = A_i B_i for the n (<= kLpGroupMax) products g[0..n-1], all of the given kind; each C_i is bit
+// for bit the result gemm_lp gives for g[i] alone.
+hipError_t gemm_lp_grouped(const LpGemmArgs* g, int n, int prec, Orient ob, int outp, unsigned* ctr,
+                           hipStream_t s);
+
+// Lock-step grouping of the reduced-precision products of several decompositions of one shape
+// (served requests admitted together), each running on its own host thread and stream.  A member's
+// product call waits until every active member has made its call of the round; the last to arrive
+// launches the round's products as grouped persistent grids on the group's stream, after that
+// stream has waited for each member's stream, and every member's stream then waits for the grids.
+// Each product's result is bit for bit the one it gets alone.  A member that stops calling (done, or
+// failed) leaves, so that the others never wait for it.  Thread-local: lp_group_set(g) makes the
+// calling thread's products go through g (nullptr: ordinary launches).
+class LpGrouper {
+  public:
+    LpGrouper(int members, int device);
+    ~LpGrouper();
+    bool ok() const { return ok_; }
+    hipError_t gemm(const LpGemmArgs& g, int prec, Orient ob, int outp, hipStream_t member_stream);
+    void leave();
+    int64_t launches() const { return launches_; }
+    int64_t products() const { return products_; }
+
+  private:
+    struct Item {
+        LpGemmArgs g;
+        int prec, outp;
+        Orient ob;
+    };
+    void launch_locked();
+    std::mutex mu_;
+    std::condition_variable cv_;
+    int members_, arrived_ = 0;
+    uint64_t gen_ = 0;
+    std::vector<Item> items_;
+    std::vector<hipEvent_t> in_ev_;
+    hipEvent_t done_ev_ = nullptr;
+    hipStream_t gs_ = nullptr;
+    unsigned* ctr_ = nullptr;
+    hipError_t result_ = hipSuccess;
+    bool ok_ = false;
+    int64_t launches_ = 0, products_ = 0;
+};
+void lp_group_set(LpGrouper* g);
+LpGrouper* lp_group_current();
+
 // Outputs: float, or the 16-bit type of the sweep's intermediates (BF16 for BF16 and FP8 operands,
 // FP16 for FP16 operands); other combinations return hipErrorInvalidValue.
 hipError_t gemm_lp(const LpGemmArgs& g, int prec, Orient ob, int outp, hipStream_t s);
@@ -34,6 +102,9 @@ constexpr int kLpGemmK = 64;
 hipError_t gemm_lp_bf16(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
 hipError_t gemm_lp_f16(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
 hipError_t gemm_lp_fp8(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipStream_t s);
+hipError_t gemm_lp_grouped_bf16(const LpGroupArgs& a, Orient ob, int outp, bool vec, hipStream_t s);
+hipError_t gemm_lp_grouped_f16(const LpGroupArgs& a, Orient ob, int outp, bool vec, hipStream_t s);
+hipError_t gemm_lp_grouped_fp8(const LpGroupArgs& a, Orient ob, int outp, bool vec, hipStream_t s);
 
 // out[i] = enc(x[i] / scale[i % L]) (scale nullable)
 hipError_t to_lowp(const float* x, int64_t n, int prec, int L, const float* scale, void* out, hipStream_t s);

@@ -351,6 +351,34 @@ hipError_t gemm_lp(const LpGemmArgs& gin, int prec, Orient ob, int outp, hipStre
     return hipErrorInvalidValue;
 }
 
+hipError_t gemm_lp_grouped(const LpGemmArgs* gin, int n, int prec, Orient ob, int outp, unsigned* ctr,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > kLpGroupMax || !ctr) return hipErrorInvalidValue;
+    const int es = (prec == LP_FP8) ? 1 : 2;
+    LpGroupArgs a{};
+    a.n = 0;
+    a.ctr = ctr;
+    a.start[0] = 0;
+    bool vec = true;
+    for (int i = 0; i < n; ++i) {
+        LpGemmArgs g = gin[i];
+        if (g.M <= 0 || g.N <= 0) continue;
+        if (g.k_split <= 0 || g.k_split > g.K) g.k_split = g.K > 0 ? g.K : 1;
+        if (g.k_split % kLpGemmK != 0 && g.k_split != g.K) return hipErrorInvalidValue;
+        if (g.sb && g.sb_mod <= 0) return hipErrorInvalidValue;
+        vec = vec && desc_vec_ok(g.a, es) && desc_vec_ok(g.b, es);
+        a.p[a.n] = g;
+        a.start[a.n + 1] = a.start[a.n] + lp_work_items(g);
+        ++a.n;
+    }
+    if (a.n == 0) return hipSuccess;
+    if (prec == LP_BF16) return gemm_lp_grouped_bf16(a, ob, outp, vec, s);
+    if (prec == LP_F16) return gemm_lp_grouped_f16(a, ob, outp, vec, s);
+    if (prec == LP_FP8) return gemm_lp_grouped_fp8(a, ob, outp, vec, s);
+    return hipErrorInvalidValue;
+}
+
 static unsigned grid_for(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));

@@ -10,6 +10,7 @@
 // latter is loaded as 4 (k) x 8 (n) register blocks and transposed on the way into LDS.  The next
 // k-tile is prefetched into registers while the current one is multiplied.
 #pragma once
+#include <algorithm>
 #include <type_traits>
 
 #include "tk_lowp_impl.h"
@@ -32,8 +33,9 @@ constexpr int LBN = 128, LBK = kLpGemmK;
 // Workgroups whose 128 x 128 output tile lies inside C (and whose operands allow vector loads) run
 // their full 64-wide k-tiles through a loader without bounds checks; the last, partial k-tile and
 // the edge tiles take the checked loader.
-template <int P, int OB, int OUTP, bool VEC, int NST, int OCC>
-__global__ __launch_bounds__(256, OCC) void gemm_lp_kernel(LpGemmArgs g) {
+// One output tile (logical tile index t, k split z) of C; every thread of the workgroup calls it.
+template <int P, int OB, int OUTP, bool VEC, int NST>
+__device__ __forceinline__ void gemm_lp_tile(const LpGemmArgs& g, int64_t t, int64_t z) {
     typedef typename Codec<P>::S S;
     typedef typename Vec8<P>::T V8;
     constexpr int ES = (int)sizeof(S);
@@ -50,7 +52,6 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_kernel(LpGemmArgs g) {
 
     const int64_t tilesM = (g.M + BMT - 1) / BMT;
     const int64_t tilesN = (g.N + LBN - 1) / LBN;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int64_t tm, tn;
     if (g.lower_only) {
         tm = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_kernel(LpGemmArgs g) {
     }
     if (tn >= tilesN || tm >= tilesM) return;
     const int64_t m0 = tm * BMT, n0 = tn * LBN;
-    const int64_t kbeg = (int64_t)blockIdx.z * g.k_split;
+    const int64_t kbeg = z * g.k_split;
     const int64_t kend = (kbeg + g.k_split < g.K) ? kbeg + g.k_split : g.K;
     const bool full = VEC && m0 + BMT <= g.M && n0 + LBN <= g.N;
 
@@ -271,12 +272,43 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_kernel(LpGemmArgs g) {
                 if (m >= g.M) continue;
                 float val = acc[i][j][v] * cs;
                 if (g.sa) val *= g.sa[m];
-                const int64_t off = (int64_t)blockIdx.z * g.c_zstride + m * g.c.ld + co;
+                const int64_t off = z * g.c_zstride + m * g.c.ld + co;
                 if (OUTP == LP_F32OUT) ((float*)cbase)[off] = val;
                 else if (OUTP == LP_BF16) ((uint16_t*)cbase)[off] = enc_bf16(val);
                 else ((uint16_t*)cbase)[off] = enc_f16(val);
             }
         }
+    }
+}
+
+template <int P, int OB, int OUTP, bool VEC, int NST, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_lp_kernel(LpGemmArgs g) {
+    gemm_lp_tile<P, OB, OUTP, VEC, NST>(g, xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
+}
+
+// Persistent grouped launch: each workgroup claims work items (tile, split) of the group's products
+// from a device counter until none is left; items are numbered product by product.  The last
+// workgroup to finish clears both counters for the next launch on the stream.
+template <int P, int OB, int OUTP, bool VEC, int NST, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_lp_grouped_kernel(LpGroupArgs a) {
+    __shared__ int64_t claim;
+    for (;;) {
+        if (threadIdx.x == 0) claim = (int64_t)atomicAdd(a.ctr, 1u);
+        __syncthreads();
+        const int64_t w = claim;
+        __syncthreads();
+        if (w >= a.start[a.n]) break;
+        int p = 0;
+        while (p + 1 < a.n && a.start[p + 1] <= w) ++p;
+        const int64_t local = w - a.start[p];
+        const int64_t tilesM = (a.p[p].M + 127) / 128;
+        const int64_t tilesN = (a.p[p].N + LBN - 1) / LBN;
+        const int64_t tiles = a.p[p].lower_only ? tilesM * (tilesM + 1) / 2 : tilesM * tilesN;
+        gemm_lp_tile<P, OB, OUTP, VEC, NST>(a.p[p], local % tiles, local / tiles);
+    }
+    if (threadIdx.x == 0 && atomicAdd(a.ctr + 1, 1u) == gridDim.x - 1) {
+        atomicExch(a.ctr, 0u);
+        atomicExch(a.ctr + 1, 0u);
     }
 }
 
@@ -309,6 +341,41 @@ hipError_t launch_lp(const LpGemmArgs& g, bool vec, hipStream_t s) {
     return e != hipSuccess ? e : launch(c);
 }
 
+// the grouped form of launch_lp: the LDS staging is the one kept for the first product's shape (or the
+// heuristic's, never measured here), the grid is what stays resident (three workgroups per CU)
+template <int P, int OB, int OUTP, int NST>
+hipError_t launch_lp_grouped_v(const LpGroupArgs& a, bool vec, hipStream_t s) {
+    const int64_t items = a.start[a.n];
+    if (items == 0) return hipSuccess;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || cus <= 0)
+        cus = 256;
+    const int64_t per = (NST == 2 || !vec) ? 2 : 3;
+    const unsigned grid = (unsigned)std::min<int64_t>(items, per * cus);
+    if (vec) {
+        if (NST == 2) hipLaunchKernelGGL((gemm_lp_grouped_kernel<P, OB, OUTP, true, 2, 2>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((gemm_lp_grouped_kernel<P, OB, OUTP, true, 1, 3>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((gemm_lp_grouped_kernel<P, OB, OUTP, false, NST, 2>), dim3(grid), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int P, int OB, int OUTP>
+hipError_t launch_lp_grouped(const LpGroupArgs& a, bool vec, hipStream_t s) {
+    const LpGemmArgs& g = a.p[0];
+    const int64_t shape[5] = {g.M, g.N, g.K, g.k_split,
+                              1000 * P + 100 * OB + 10 * OUTP + (vec ? 1 : 0) + (g.lower_only ? 10000 : 0)};
+    hipError_t e = hipSuccess;
+    const bool was = tune_enabled();
+    tune_set_enabled(false);
+    const int c = tune_choose(kTuneLpTile, shape, 2, 0, s, [](int) { return hipSuccess; }, &e);
+    tune_set_enabled(was);
+    if (e != hipSuccess) return e;
+    return c == 1 ? launch_lp_grouped_v<P, OB, OUTP, 2>(a, vec, s) : launch_lp_grouped_v<P, OB, OUTP, 1>(a, vec, s);
+}
+
 // outputs: FP32, or the 16-bit type of the sweep's intermediates (BF16 for BF16 and FP8 operands, FP16
 // for FP16 operands)
 template <int P, int OB>
@@ -316,6 +383,13 @@ hipError_t by_out(const LpGemmArgs& g, int outp, bool vec, hipStream_t s) {
     constexpr int LP16 = (P == LP_F16) ? LP_F16 : LP_BF16;
     if (outp == LP_F32OUT) return launch_lp<P, OB, LP_F32OUT>(g, vec, s);
     if (outp == LP16) return launch_lp<P, OB, LP16>(g, vec, s);
+    return hipErrorInvalidValue;
+}
+template <int P, int OB>
+hipError_t by_out_grouped(const LpGroupArgs& a, int outp, bool vec, hipStream_t s) {
+    constexpr int LP16 = (P == LP_F16) ? LP_F16 : LP_BF16;
+    if (outp == LP_F32OUT) return launch_lp_grouped<P, OB, LP_F32OUT>(a, vec, s);
+    if (outp == LP16) return launch_lp_grouped<P, OB, LP16>(a, vec, s);
     return hipErrorInvalidValue;
 }
 

@@ -7,4 +7,8 @@ hipError_t gemm_lp_bf16(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipS
     return ob == KM ? by_out<LP_BF16, KM>(g, outp, vec, s) : by_out<LP_BF16, MK>(g, outp, vec, s);
 }
 
+hipError_t gemm_lp_grouped_bf16(const LpGroupArgs& a, Orient ob, int outp, bool vec, hipStream_t s) {
+    return ob == KM ? by_out_grouped<LP_BF16, KM>(a, outp, vec, s) : by_out_grouped<LP_BF16, MK>(a, outp, vec, s);
+}
+
 }  // namespace tk

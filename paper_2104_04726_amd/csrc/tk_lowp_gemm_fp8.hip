@@ -8,4 +8,9 @@ hipError_t gemm_lp_fp8(const LpGemmArgs& g, Orient ob, int outp, bool vec, hipSt
     return by_out<LP_FP8, KM>(g, outp, vec, s);
 }
 
+hipError_t gemm_lp_grouped_fp8(const LpGroupArgs& a, Orient ob, int outp, bool vec, hipStream_t s) {
+    if (ob != KM) return hipErrorInvalidValue;
+    return by_out_grouped<LP_FP8, KM>(a, outp, vec, s);
+}
+
 }  // namespace tk

@@ -7,6 +7,12 @@
 // ordered allocations, so no device-wide synchronisation from allocation), copies the outputs
 // out, frees its device memory and returns the footprint to the budget.  Requests queue strictly
 // in arrival order: a large request at the head is not overtaken by smaller ones behind it.
+//
+// Groups: when the head may be grouped (reduced-precision sweeps, no tolerance), the worker also
+// admits the requests right behind it that have the same shape class and fit in the budget (up to
+// group_requests in all).  It runs the first itself and each other member in a thread of its own on
+// a pooled helper context; the members' sweep products are launched in lock step as grouped
+// persistent grids over all their tiles (LpGrouper), and their sweeps are not replayed as graphs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,20 +22,29 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/tucker.h"
+#include "tk_lowp.h"
 
 void tk_ctx_set_async_alloc(tucker_ctx* ctx, bool on);
 void tk_ctx_release_workspace(tucker_ctx* ctx);
 void tk_ctx_set_run_options(tucker_ctx* ctx, tucker_precision precision, int refine_sweeps);
+void tk_ctx_set_graphs(tucker_ctx* ctx, bool on);
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// requests admitted together that share grouped launches of their reduced-precision products
+struct Group {
+    tk::LpGrouper lp;
+    Group(int members, int device) : lp(members, device) {}
+};
 
 struct Job {
     uint64_t id = 0;
@@ -37,7 +52,22 @@ struct Job {
     size_t footprint = 0;
     bool done = false;
     tucker_result res{};
+    std::shared_ptr<Group> grp;
 };
+
+// requests that may run as one group: same shape and schedule, reduced-precision sweeps, no
+// data-dependent stopping (every member makes the same sequence of products)
+bool groupable(const tucker_request& q) {
+    return q.precision != TUCKER_FP32 && !(q.tol > 0.0) && q.max_iters > 0;
+}
+bool same_class(const tucker_request& a, const tucker_request& b) {
+    if (a.ndim != b.ndim || a.precision != b.precision || a.max_iters != b.max_iters ||
+        a.refine_sweeps != b.refine_sweeps || a.tol != b.tol)
+        return false;
+    for (int n = 0; n < a.ndim; ++n)
+        if (a.dims[n] != b.dims[n] || a.ranks[n] != b.ranks[n]) return false;
+    return true;
+}
 
 int64_t prod(const int64_t* d, int n) {
     int64_t p = 1;
@@ -59,6 +89,8 @@ struct tucker_server {
     std::condition_variable cv_work;   // workers: queue or budget changed
     std::condition_variable cv_done;   // waiters: a job finished
     std::deque<Job*> queue;
+    std::mutex helper_mu;              // contexts (each with its own stream) for group members
+    std::vector<std::pair<tucker_ctx*, hipStream_t>> helpers_free, helpers_all;
     std::map<uint64_t, Job*> jobs;
     uint64_t next_id = 1;
     size_t budget = 0, admitted = 0;
@@ -71,14 +103,18 @@ struct tucker_server {
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
-    void run_job(int slot, Job* j) {
-        tucker_ctx* ctx = ctxs[slot];
-        hipStream_t s = streams[slot];
+    void run_job(int slot, Job* j) { run_job_on(ctxs[slot], streams[slot], j); }
+
+    void run_job_on(tucker_ctx* ctx, hipStream_t s, Job* j) {
         const tucker_request& q = j->req;
         tucker_result& r = j->res;
         r.t_start = now();
         const int N = q.ndim;
         const int64_t xn = prod(q.dims, N), gn = prod(q.ranks, N);
+        if (j->grp) {
+            tk::lp_group_set(&j->grp->lp);
+            tk_ctx_set_graphs(ctx, false);
+        }
         float* dx = nullptr;
         float* dg = nullptr;
         std::vector<float*> df(N, nullptr);
@@ -120,39 +156,146 @@ struct tucker_server {
         if (dg) (void)hipFreeAsync(dg, s);
         for (float* p : df)
             if (p) (void)hipFreeAsync(p, s);
+        if (j->grp) {
+            j->grp->lp.leave();
+            tk::lp_group_set(nullptr);
+            tk_ctx_set_graphs(ctx, opt.use_graphs != 0);
+        }
         tk_ctx_release_workspace(ctx);
         (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
         r.t_finish = now();
     }
 
+    // a context and stream for one more group member: from the pool, or created (nullptr on failure)
+    bool acquire_helper(std::pair<tucker_ctx*, hipStream_t>& out) {
+        {
+            std::lock_guard<std::mutex> lk(helper_mu);
+            if (!helpers_free.empty()) {
+                out = helpers_free.back();
+                helpers_free.pop_back();
+                return true;
+            }
+        }
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        tucker_options co;
+        tucker_default_options(&co);
+        co.device = opt.device;
+        co.inner_iters = opt.inner_iters;
+        co.init_iters = opt.init_iters;
+        co.seed = opt.seed;
+        co.use_graphs = opt.use_graphs;
+        co.autotune = opt.autotune;
+        co.stream = st;
+        tucker_ctx* c = nullptr;
+        if (tucker_create(&co, &c) != TUCKER_OK) {
+            (void)hipStreamDestroy(st);
+            return false;
+        }
+        tk_ctx_set_async_alloc(c, true);
+        out = {c, st};
+        std::lock_guard<std::mutex> lk(helper_mu);
+        helpers_all.push_back(out);
+        return true;
+    }
+    void release_helper(const std::pair<tucker_ctx*, hipStream_t>& h) {
+        std::lock_guard<std::mutex> lk(helper_mu);
+        helpers_free.push_back(h);
+    }
+
+    // admit j (the queue head, already popped) and, when it may be grouped, the consecutive queued
+    // requests of its class that fit in the budget, up to opt.group_requests in all; mu held
+    std::vector<Job*> admit_locked(Job* j, int slot) {
+        std::vector<Job*> members{j};
+        auto take = [&](Job* x) {
+            admitted += x->footprint;
+            ++running;
+            x->res.t_admit = now();
+            x->res.slot = slot;
+        };
+        take(j);
+        if (opt.group_requests > 1 && groupable(j->req)) {
+            while (!queue.empty() && (int)members.size() < opt.group_requests &&
+                   same_class(queue.front()->req, j->req) && admitted + queue.front()->footprint <= budget) {
+                Job* x = queue.front();
+                queue.pop_front();
+                take(x);
+                members.push_back(x);
+            }
+        }
+        stats.peak_admitted_bytes = std::max(stats.peak_admitted_bytes, admitted);
+        stats.peak_running = std::max(stats.peak_running, running);
+        return members;
+    }
+
+    void finish_locked(Job* j) {
+        admitted -= j->footprint;
+        --running;
+        j->done = true;
+        stats.completed += 1;
+        if (j->res.status != TUCKER_OK) stats.failed += 1;
+    }
+
+    // members[0] runs on the worker's own context; the others on helper contexts in threads of their
+    // own, all in lock step through one LpGrouper (a member that cannot get a context fails alone)
+    void run_group(int slot, const std::vector<Job*>& members) {
+        const int g = (int)members.size();
+        auto grp = std::make_shared<Group>(g, opt.device);
+        if (!grp->lp.ok()) {
+            for (Job* x : members) run_job(slot, x);   // one after another, ungrouped
+            return;
+        }
+        for (Job* x : members) x->grp = grp;
+        std::vector<std::thread> th;
+        std::vector<std::pair<tucker_ctx*, hipStream_t>> hs(g);
+        for (int k = 1; k < g; ++k) {
+            if (!acquire_helper(hs[k])) {
+                hs[k] = {nullptr, nullptr};
+                set_error(members[k]->res, TUCKER_ERR_DEVICE, "no context for a group member");
+                grp->lp.leave();
+                continue;
+            }
+            th.emplace_back([this, k, &hs, &members] {
+                (void)hipSetDevice(opt.device);
+                run_job_on(hs[k].first, hs[k].second, members[k]);
+            });
+        }
+        run_job(slot, members[0]);
+        for (auto& t : th) t.join();
+        for (int k = 1; k < g; ++k)
+            if (hs[k].first) release_helper(hs[k]);
+        std::lock_guard<std::mutex> lk(mu);
+        stats.grouped_requests += g;
+        stats.group_launches += grp->lp.launches();
+        stats.grouped_products += grp->lp.products();
+    }
+
     void worker(int slot) {
         (void)hipSetDevice(opt.device);
         for (;;) {
-            Job* j = nullptr;
+            std::vector<Job*> members;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
                     return stop || (!queue.empty() && admitted + queue.front()->footprint <= budget);
                 });
                 if (stop) return;
-                j = queue.front();
+                Job* j = queue.front();
                 queue.pop_front();
-                admitted += j->footprint;
-                ++running;
-                stats.peak_admitted_bytes = std::max(stats.peak_admitted_bytes, admitted);
-                stats.peak_running = std::max(stats.peak_running, running);
-                j->res.t_admit = now();
-                j->res.slot = slot;
+                members = admit_locked(j, slot);
             }
-            run_job(slot, j);
+            if (members.size() == 1) run_job(slot, members[0]);
+            else run_group(slot, members);
             {
                 std::lock_guard<std::mutex> lk(mu);
-                admitted -= j->footprint;
-                --running;
-                j->done = true;
-                stats.completed += 1;
-                if (j->res.status != TUCKER_OK) stats.failed += 1;
+                for (Job* x : members) {
+                    finish_locked(x);
+                    x->grp.reset();
+                }
             }
             cv_work.notify_all();
             cv_done.notify_all();
@@ -173,6 +316,7 @@ void tucker_default_server_options(tucker_server_options* o) {
     o->seed = 0x5eedull;
     o->use_graphs = 1;
     o->autotune = 1;
+    o->group_requests = 0;
 }
 
 tucker_status tucker_server_create(const tucker_server_options* opts, tucker_server** out) {
@@ -181,7 +325,8 @@ tucker_status tucker_server_create(const tucker_server_options* opts, tucker_ser
     tucker_server_options o;
     tucker_default_server_options(&o);
     if (opts) o = *opts;
-    if (o.slots < 1 || o.slots > 64 || o.inner_iters < 1 || o.init_iters < 1 || o.device < 0)
+    if (o.slots < 1 || o.slots > 64 || o.inner_iters < 1 || o.init_iters < 1 || o.device < 0 ||
+        o.group_requests < 0 || o.group_requests > tk::kLpGroupMax)
         return TUCKER_ERR_INVALID_ARG;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= o.device) {
@@ -314,6 +459,10 @@ tucker_status tucker_server_destroy(tucker_server* srv) {
     for (auto& t : srv->workers)
         if (t.joinable()) t.join();
     for (tucker_ctx* c : srv->ctxs) tucker_destroy(c);
+    for (auto& h : srv->helpers_all) {
+        tucker_destroy(h.first);
+        (void)hipStreamDestroy(h.second);
+    }
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
     for (auto& kv : srv->jobs) delete kv.second;
     delete srv;
