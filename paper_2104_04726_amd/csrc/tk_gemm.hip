@@ -103,6 +103,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                        (BM * BK == 512 || BM * BK == 1024)),
                   "vector loads need whole float4 per thread");
     constexpr bool VK2 = VECK && BM * BK == 1024;   // every thread loads one vector of A and one of B
+    // KMV: both operands k-major (KM) FP32 with contiguous column runs of KW (VEC 4: runs of 4 as 16-byte
+    // loads; VEC 3: runs only 2-aligned, e.g. 42-long folded pixel fibres, as 8-byte loads)
+    constexpr bool KMV = (VEC == 4 || VEC == 3) && OA == KM;
+    constexpr int KW = (VEC == 3) ? 2 : 4;
+    static_assert(VEC != 3 || (OA == KM && OB == KM && sizeof(TA) == 4 && sizeof(TB) == 4 &&
+                               (BM * BK) % 512 == 0 && (BN * BK) % 512 == 0),
+                  "8-byte k-major loads need FP32 operands and whole float2 per thread");
     // D2: FP64 operands with 2-aligned contiguous runs (64 x 64 x 16 tiles): 16-byte loads of two
     // doubles, two per operand per thread.  KM tile (16 k-rows x 64): row tid / 32 + 8 u, column
     // pair tid % 32; MK tile (64 rows x 16 k): row tid / 8 + 32 u, k pair tid % 8.
@@ -152,11 +159,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // KM: the column (m or n) is fixed for the whole K loop
     int64_t a_fix = 0, b_fix = 0;
     bool a_colok = true, b_colok = true;
-    if (OA == KM && VEC != 4) {
+    if (OA == KM && !KMV) {
         a_colok = (m0 + a_c) < g.M;
         a_fix = a_colok ? coloff(g.a, m0 + a_c) : 0;
     }
-    if (OB == KM && VEC != 4) {
+    if (OB == KM && !KMV) {
         b_colok = (n0 + b_c) < g.N;
         b_fix = b_colok ? coloff(g.b, n0 + b_c) : 0;
     }
@@ -198,17 +205,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
         return v;
     };
-    // VEC mapping: thread -> column group c4 (4 columns), rows r0 + step * u
-    constexpr int A4 = BM / 4, B4 = BN / 4;
+    // KMV mapping: thread -> column group c4 (KW columns), rows r0 + step * u
+    constexpr int A4 = BM / KW, B4 = BN / KW;
     constexpr int av_step = 256 / A4, bv_step = 256 / B4;
     const int av_c4 = tid % A4, av_r0 = tid / A4;
     const int bv_c4 = tid % B4, bv_r0 = tid / B4;
     int64_t av_fix = 0, bv_fix = 0;
-    int av_n = 0, bv_n = 0;      // valid columns of the thread's group (0..4)
-    if (VEC == 4 && OA == KM) {
-        const int64_t ca = m0 + 4 * av_c4, cb = n0 + 4 * bv_c4;
-        av_n = (int)((g.M - ca) < 4 ? ((g.M - ca) > 0 ? (g.M - ca) : 0) : 4);
-        bv_n = (int)((g.N - cb) < 4 ? ((g.N - cb) > 0 ? (g.N - cb) : 0) : 4);
+    int av_n = 0, bv_n = 0;      // valid columns of the thread's group (0..KW)
+    if (KMV) {
+        const int64_t ca = m0 + KW * av_c4, cb = n0 + KW * bv_c4;
+        av_n = (int)((g.M - ca) < KW ? ((g.M - ca) > 0 ? (g.M - ca) : 0) : KW);
+        bv_n = (int)((g.N - cb) < KW ? ((g.N - cb) > 0 ? (g.N - cb) : 0) : KW);
         av_fix = av_n > 0 ? coloff(g.a, ca) : 0;
         bv_fix = bv_n > 0 ? coloff(g.b, cb) : 0;
     }
@@ -293,21 +300,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         int count) {
         for (int u = 0; u < count; ++u) {
             const int64_t k = k0 + r0 + step * u;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < kend && nvalid > 0) {
-                const TA* src = p + k * d.ld + fix;
-                if (nvalid == 4) {
-                    v = *(const float4*)src;
-                } else {
-                    v.x = src[0];
-                    if (nvalid > 1) v.y = src[1];
-                    if (nvalid > 2) v.z = src[2];
+            if constexpr (KW == 4) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k < kend && nvalid > 0) {
+                    const TA* src = p + k * d.ld + fix;
+                    if (nvalid == 4) {
+                        v = *(const float4*)src;
+                    } else {
+                        v.x = src[0];
+                        if (nvalid > 1) v.y = src[1];
+                        if (nvalid > 2) v.z = src[2];
+                    }
                 }
+                dst[4 * u + 0] = v.x;
+                dst[4 * u + 1] = v.y;
+                dst[4 * u + 2] = v.z;
+                dst[4 * u + 3] = v.w;
+            } else {
+                float2 v = make_float2(0.f, 0.f);
+                if (k < kend && nvalid > 0) {
+                    const TA* src = p + k * d.ld + fix;
+                    if (nvalid == 2) v = *(const float2*)src;
+                    else v.x = src[0];
+                }
+                dst[2 * u + 0] = v.x;
+                dst[2 * u + 1] = v.y;
             }
-            dst[4 * u + 0] = v.x;
-            dst[4 * u + 1] = v.y;
-            dst[4 * u + 2] = v.z;
-            dst[4 * u + 3] = v.w;
         }
     };
     auto load_tiles = [&](int64_t k0) {
@@ -362,9 +380,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             }
             return;
         }
-        if constexpr (VEC == 4 && OA == KM) {
-            load_vec((const TA*)pa, g.a, av_fix, av_n, av_r0, av_step, k0, ra, EA / 4);
-            load_vec((const TA*)pb, g.b, bv_fix, bv_n, bv_r0, bv_step, k0, rb, EB / 4);
+        if constexpr (KMV) {
+            load_vec((const TA*)pa, g.a, av_fix, av_n, av_r0, av_step, k0, ra, EA / KW);
+            load_vec((const TA*)pb, g.b, bv_fix, bv_n, bv_r0, bv_step, k0, rb, EB / KW);
             return;
         }
         if (OA == KM) {
@@ -443,6 +461,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 T* db = Bs + row * LDB + 2 * v2_kw;
                 db[0] = (T)v2b[u].x;
                 db[1] = (T)v2b[u].y;
+            }
+            return;
+        }
+        if constexpr (VEC == 3 && OA == KM) {
+#pragma unroll
+            for (int u = 0; u < EA / 2; ++u) {
+                T* d = &As[(av_r0 + av_step * u) * LDA + 2 * av_c4];
+                if constexpr (sizeof(T) == 4) *(float2*)d = make_float2(ra[2 * u], ra[2 * u + 1]);
+                else *(double2*)d = make_double2(ra[2 * u], ra[2 * u + 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < EB / 2; ++u) {
+                T* d = &Bs[(bv_r0 + bv_step * u) * LDB + 2 * bv_c4];
+                if constexpr (sizeof(T) == 4) *(float2*)d = make_float2(rb[2 * u], rb[2 * u + 1]);
+                else *(double2*)d = make_double2(rb[2 * u], rb[2 * u + 1]);
             }
             return;
         }
@@ -630,6 +663,20 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
         const bool same_seg = !(OA == MK && BM * BK == 1024) || g.a.seg == g.b.seg;
         if (km_vec_ok(g.a) && km_vec_ok(g.b) && same_seg && (OA == KM || g.k_split % 4 == 0)) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 4>), grid, dim3(256), 0, s,
+                               g);
+            return hipGetLastError();
+        }
+    }
+    constexpr bool can_km2 = OA == KM && OB == KM && sizeof(TA) == 4 && sizeof(TB) == 4 && (BM * BK) % 512 == 0 &&
+                             (BN * BK) % 512 == 0;
+    if constexpr (can_km2) {
+        // k-major rows read as 2-aligned runs of 2 columns (8-byte loads), e.g. 42-long folded fibres
+        auto ok2 = [](const Desc& d) {
+            const bool segok = d.seg >= (int64_t(1) << 61) || (d.seg % 2 == 0 && d.segstride % 2 == 0);
+            return segok && d.ld % 2 == 0 && (((uintptr_t)d.ptr) & 7) == 0;
+        };
+        if (ok2(g.a) && ok2(g.b)) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 3>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
         }
