@@ -81,8 +81,12 @@ typedef struct {
     int refine_sweeps;           /* FP32 sweeps appended after reduced-precision sweeps       */
     int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1);
                                     with inner_tol > 0, the most steps an update may take     */
-    int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD;
-                                    with inner_tol > 0, the most steps a start may take       */
+    int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD of a
+                                    large mode (from a seeded random basis, no oversampling):
+                                    directions whose eigenvalue gap is wide converge, those at
+                                    a nearly degenerate rank boundary need not, so the start is
+                                    the T-HOSVD up to rotations inside that boundary; with
+                                    inner_tol > 0, the most steps a start may take            */
     double inner_tol;            /* 0: fixed step counts.  > 0: each large-mode update, cold or
                                     warm, forms its Gram S and iterates until the invariant-
                                     subspace residual ||S U - U (U^T S U)||_F <= inner_tol ||S||_F
@@ -187,7 +191,8 @@ tucker_status tucker_destroy(tucker_ctx* ctx);
 /* Tucker decomposition by HOOI (T-HOSVD start, then up to max_iters sweeps).
  *   tensor   device, prod(dims) floats, read-only.
  *   dims     host, ndim entries; ranks host, ndim entries.
- *   max_iters number of sweeps; 0 returns the start (T-HOSVD, or ST-HOSVD per tucker_options.start).
+ *   max_iters number of sweeps; 0 returns the start (T-HOSVD, or ST-HOSVD per tucker_options.start;
+ *            large modes by init_iters steps of orthogonal iteration, see tucker_options).
  *   tol      stop early when |fit_k - fit_{k-1}| < tol (tol = 0: run all sweeps).  With tol > 0
  *            each sweep's fit is the explicit residual fit (one more expanding pass per sweep);
  *            with tol = 0 it is the cheaper 1 - sqrt(||X||^2 - ||G||^2) / ||X|| from the FP32 core,
