@@ -123,6 +123,7 @@ struct Plan {
     int prec = 0, ip = 0;
     int64_t R23p = 0;        // R3 R4 rounded up to 8: padded fibre length of T34 / Y0 / Y1
     int64_t Lp = 0;          // s3 s4 rounded up to 8: padded fibre length of T1 (zero padding)
+    bool lp_start = false;   // reduced-precision runs: the start's Grams of X from a padded copy in T34
     void *Xlp = nullptr, *T34lp = nullptr, *Y0lp = nullptr, *Y1lp = nullptr, *T1lp = nullptr;
     void *U1t = nullptr, *U2t = nullptr, *U1t8 = nullptr;   // transposed factor copies (rows padded to 8)
     float *xscale = nullptr, *u1scale = nullptr, *spart = nullptr;
@@ -320,6 +321,11 @@ void build_plan(Plan& p, Arena& a) {
             p.U1t8 = a.take<uint8_t>(R0 * s0p);
             p.u1scale = a.take<float>(R0);
             p.Pf_elems = std::max(lp_gram_partials(s0, R1 * p.R23p), lp_gram_partials(s1, R0 * p.R23p));
+            // the start's Grams of X in the sweeps' reduced precision: a copy of X with zero-padded
+            // fibres (16-bit, Lp long) fits where the FP32 T34 goes, which the start does not use
+            p.lp_start = p.kind[0] == LARGE && p.kind[1] == LARGE && 2 * p.Lp <= 4 * R23;
+            if (p.lp_start)
+                p.Pf_elems = std::max(p.Pf_elems, std::max(lp_gram_partials(s0, s1 * p.Lp), lp_gram_partials(s1, s0 * p.Lp)));
             p.Pf = a.take<float>(p.Pf_elems);
         }
     } else {
@@ -999,6 +1005,29 @@ void core_norm_and_fit(Run& r, double* fit_slot) {
 }
 
 // ------------------------------------------------------------------ T-HOSVD initialisation
+void lp_gram(Run& r, Desc y, int64_t srows, int64_t K, int stage);
+
+// Gram of X for the start of large mode n (0 or 1 of a tree shape): in the sweeps' reduced precision
+// from the padded copy made by lp_start_copy (FP32 partial sums over k splits, summed in FP64), else in
+// FP64 from the FP32 tensor
+void start_gram(Run& r, int n) {
+    Plan& p = r.p;
+    if (!p.lp_start || n > 1) {
+        gram(r, r.X, p.s, p.N, n);
+        return;
+    }
+    const int64_t s0 = p.s[0], s1 = p.s[1], Lp = p.Lp;
+    const void* xp = p.T34;
+    if (n == 0) lp_gram(r, plain(xp, s1 * Lp), s0, s1 * Lp, -1);
+    else lp_gram(r, folded(xp, Lp, Lp, s1 * Lp), s1, s0 * Lp, -1);
+}
+void lp_start_copy(Run& r) {
+    Plan& p = r.p;
+    if (!p.lp_start) return;
+    const int64_t L = p.s[2] * p.s[3];
+    TK_HIP(to_lowp_padded(r.X, p.s[0] * p.s[1], (int)L, (int)p.Lp, p.ip, p.T34, r.st));
+}
+
 void thosvd(Run& r) {
     Plan& p = r.p;
     // modes from `from` on, in order.  Tree shapes: the Grams of the two small trailing modes come
@@ -1019,11 +1048,12 @@ void thosvd(Run& r) {
                 }
                 TK_HIP(pair_mode_gram(p.F, (int)p.s[2], (int)p.s[3], nullptr, 0, n == 2 ? 3 : 4, p.S64, r.st));
             } else {
-                gram(r, r.X, p.s, p.N, n);
+                start_gram(r, n);
             }
             update_factor(r, n, true);
         }
     };
+    lp_start_copy(r);
     if (!p.has_alt || r.inner_tol() > 0.0) {
         // (with a tolerance every step waits for the host, so the two streams could not overlap)
         modes_from(0);
@@ -1034,14 +1064,14 @@ void thosvd(Run& r) {
     // iterations then run on the second stream with that set, while the main stream, with the
     // second set (sized for mode 1), forms mode 1's Gram (its split partials sit in a buffer the
     // iterations do not use) and runs mode 1's iterations and the small modes
-    gram(r, r.X, p.s, p.N, 1);
+    start_gram(r, 1);
     fork_aux(r);
     {
         OnAux aux(r);
         update_factor(r, 1, true);
     }
     swap_oi(p);
-    gram(r, r.X, p.s, p.N, 0);
+    start_gram(r, 0);
     update_factor(r, 0, true);
     modes_from(2);
     swap_oi(p);

@@ -108,6 +108,8 @@ hipError_t gemm_lp_grouped_fp8(const LpGroupArgs& a, Orient ob, int outp, bool v
 
 // out[i] = enc(x[i] / scale[i % L]) (scale nullable)
 hipError_t to_lowp(const float* x, int64_t n, int prec, int L, const float* scale, void* out, hipStream_t s);
+// rows of L floats -> rows of Lp (>= L) BF16/FP16 values, the tail of each row zero
+hipError_t to_lowp_padded(const float* x, int64_t rows, int L, int Lp, int prec, void* out, hipStream_t s);
 // out[i] = dec(in[i]) * scale[i % L] (scale nullable)
 hipError_t from_lowp(const void* in, int64_t n, int prec, int L, const float* scale, float* out, hipStream_t s);
 // scale[l] = max_a |x[a][l]| / 448 (1 where the slice is zero); partial: nblocks * L floats

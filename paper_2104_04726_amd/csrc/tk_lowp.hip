@@ -35,6 +35,18 @@ __global__ __launch_bounds__(256) void to_lp_kernel(const float* __restrict__ x,
     }
 }
 
+// rows of L values -> rows of Lp >= L encoded values, the Lp - L tail of each row zero
+template <int P>
+__global__ __launch_bounds__(256) void to_lp_padded_kernel(const float* __restrict__ x, int64_t rows, int L, int Lp,
+                                                           typename Codec<P>::S* __restrict__ out) {
+    const int64_t n = rows * Lp;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t r = i / Lp;
+        const int j = (int)(i - r * Lp);
+        out[i] = j < L ? Codec<P>::enc(x[r * L + j]) : (typename Codec<P>::S)0;
+    }
+}
+
 // amax over fibres per position l of a (A, L) matrix -> partial[block][l]
 __global__ __launch_bounds__(256) void slice_amax_kernel(const float* __restrict__ x, int64_t A, int L,
                                                          float* __restrict__ partial) {
@@ -392,6 +404,19 @@ hipError_t to_lowp(const float* x, int64_t n, int prec, int L, const float* scal
         hipLaunchKernelGGL(to_lp_kernel<LP_F16>, dim3(grid_for(n)), dim3(256), 0, s, x, n, L, scale, (uint16_t*)out);
     else if (prec == LP_FP8)
         hipLaunchKernelGGL(to_lp_kernel<LP_FP8>, dim3(grid_for(n)), dim3(256), 0, s, x, n, L, scale, (uint8_t*)out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t to_lowp_padded(const float* x, int64_t rows, int L, int Lp, int prec, void* out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (Lp < L) return hipErrorInvalidValue;
+    const unsigned g = grid_for(rows * Lp);
+    if (prec == LP_BF16)
+        hipLaunchKernelGGL(to_lp_padded_kernel<LP_BF16>, dim3(g), dim3(256), 0, s, x, rows, L, Lp, (uint16_t*)out);
+    else if (prec == LP_F16)
+        hipLaunchKernelGGL(to_lp_padded_kernel<LP_F16>, dim3(g), dim3(256), 0, s, x, rows, L, Lp, (uint16_t*)out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
