@@ -82,11 +82,12 @@ typedef struct {
     int inner_iters;             /* orthogonal-iteration steps per large-mode update (>= 1);
                                     with inner_tol > 0, the most steps an update may take     */
     int init_iters;              /* cold-start orthogonal-iteration steps for the T-HOSVD of a
-                                    large mode (from a seeded random basis, no oversampling):
-                                    directions whose eigenvalue gap is wide converge, those at
-                                    a nearly degenerate rank boundary need not, so the start is
-                                    the T-HOSVD up to rotations inside that boundary; with
-                                    inner_tol > 0, the most steps a start may take            */
+                                    large mode (from a seeded random basis): without
+                                    oversampling, directions whose eigenvalue gap is wide
+                                    converge, those at a nearly degenerate rank boundary need
+                                    not, so the start is the T-HOSVD up to rotations inside
+                                    that boundary; with inner_tol > 0, the most steps a start
+                                    may take                                                  */
     double inner_tol;            /* 0: fixed step counts.  > 0: each large-mode update, cold or
                                     warm, forms its Gram S and iterates until the invariant-
                                     subspace residual ||S U - U (U^T S U)||_F <= inner_tol ||S||_F
@@ -121,6 +122,17 @@ typedef struct {
                                     exact.  FP32 sweeps (tol = 0) of order-4 stacks whose third
                                     mode is kept at full rank (identity factor) only, else
                                     TUCKER_ERR_UNSUPPORTED.  0 (default): ordinary sweeps.        */
+    int oversample;              /* p >= 0: the cold start of a large mode (T-HOSVD or ST-HOSVD
+                                    start) iterates on Rc = min(s_n, R_n + p) columns and ends with
+                                    a Rayleigh-Ritz step: B = U^T S U (Rc x Rc) is diagonalised in
+                                    FP64 (block Jacobi) and U_n is spanned by the Ritz vectors of
+                                    its R_n largest Ritz values.  The leading directions then
+                                    converge at the rate lam_{Rc+1} / lam_i instead of
+                                    lam_{R+1} / lam_i, which resolves close rank boundaries.  Rc
+                                    must not exceed 1024 (else TUCKER_ERR_UNSUPPORTED).  The two
+                                    large modes' starts then run one after the other on the
+                                    context's stream (the eigensolver checks its convergence on
+                                    the host).  0 (default): no oversampling, no Rayleigh-Ritz. */
 } tucker_options;
 
 /* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack
@@ -161,6 +173,8 @@ typedef struct {
                                     over the updates of the call (0 otherwise)                */
     int pp_sweeps;               /* pairwise-perturbation sweeps among the sweeps (pp_tol > 0) */
     int pp_refs;                 /* reference points (operator sets) formed                   */
+    int rr_sweeps;               /* oversample > 0: block-Jacobi sweeps of the start's
+                                    Rayleigh-Ritz steps (all large modes)                      */
     size_t workspace_bytes;      /* device workspace held by the context                      */
     double stage_ms[TUCKER_NUM_STAGES];   /* summed GPU time per stage (timing = 1)           */
     int stage_calls[TUCKER_NUM_STAGES];   /* number of timed occurrences per stage            */
@@ -177,7 +191,8 @@ void tucker_default_options(tucker_options* o);
 tucker_status tucker_validate(int ndim, const int64_t* dims, const int64_t* ranks,
                               int max_iters, double tol);
 
-/* Host-only: device workspace (bytes) a decomposition of this shape needs. */
+/* Host-only: device workspace (bytes) a decomposition of this shape needs with the default
+ * options (no oversampling, no pairwise perturbation); those options need more. */
 tucker_status tucker_workspace_size(int ndim, const int64_t* dims, const int64_t* ranks,
                                     tucker_precision precision, size_t* bytes);
 

@@ -84,7 +84,8 @@ class Context:
     def __init__(self, device: int = 0, stream=None, inner_iters: int = 1, init_iters: int = 20,
                  seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
                  refine_sweeps: int = 1, timing: bool = False, use_graphs: bool = False, inner_tol: float = 0.0,
-                 wait_spin_limit: int = 0, start: str = "thosvd", autotune: bool = False, pp_tol: float = 0.0):
+                 wait_spin_limit: int = 0, start: str = "thosvd", autotune: bool = False, pp_tol: float = 0.0,
+                 oversample: int = 0):
         import torch
         lib = _lib.lib()
         opts = _lib.Options()
@@ -107,6 +108,7 @@ class Context:
         opts.start = {"thosvd": _lib.START_THOSVD, "sthosvd": _lib.START_STHOSVD}[start]
         opts.autotune = 1 if autotune else 0
         opts.pp_tol = float(pp_tol)
+        opts.oversample = int(oversample)
         self.device = int(device)
         self._h = C.c_void_p()
         _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))

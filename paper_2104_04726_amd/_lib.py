@@ -36,6 +36,7 @@ class Options(C.Structure):
         ("start", C.c_int),
         ("autotune", C.c_int),
         ("pp_tol", C.c_double),
+        ("oversample", C.c_int),
     ]
 
 
@@ -55,6 +56,7 @@ class Stats(C.Structure):
         ("oi_residual_max", C.c_double),
         ("pp_sweeps", C.c_int),
         ("pp_refs", C.c_int),
+        ("rr_sweeps", C.c_int),
         ("workspace_bytes", C.c_size_t),
         ("stage_ms", C.c_double * 12),
         ("stage_calls", C.c_int * 12),

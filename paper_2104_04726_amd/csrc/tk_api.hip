@@ -115,6 +115,7 @@ enum ModeKind { FIXED = 0, SMALL = 1, LARGE = 2 };
 struct Plan {
     int N = 0;
     int64_t s[TUCKER_MAX_ORDER]{}, R[TUCKER_MAX_ORDER]{};
+    int64_t Rc[TUCKER_MAX_ORDER]{};     // columns of the cold start (R_n + oversampling, at most s_n)
     ModeKind kind[TUCKER_MAX_ORDER]{};
     bool tree = false;
     int max_iters = 0;
@@ -196,13 +197,13 @@ int64_t max_large_s(const Plan& p) {
 int64_t max_large_sR(const Plan& p) {
     int64_t m = 0;
     for (int n = 0; n < p.N; ++n)
-        if (p.kind[n] == LARGE) m = std::max(m, p.s[n] * p.R[n]);
+        if (p.kind[n] == LARGE) m = std::max(m, p.s[n] * p.Rc[n]);
     return m;
 }
 int64_t max_large_R(const Plan& p) {
     int64_t m = 0;
     for (int n = 0; n < p.N; ++n)
-        if (p.kind[n] == LARGE) m = std::max(m, p.R[n]);
+        if (p.kind[n] == LARGE) m = std::max(m, p.Rc[n]);
     return m;
 }
 
@@ -232,6 +233,7 @@ constexpr int64_t kGramFallbackCapacity = 768;
 constexpr double kGramSplitOverheadK = 256.0;   // fixed cost of a workgroup, in k steps
 constexpr int kLpScaleBlocks = 256;
 constexpr int kRefineInner = 4;
+constexpr int64_t kRitzMaxOrder = 1024;   // largest Rayleigh-Ritz matrix (block-Jacobi eigensolver)
 constexpr int kLpGramTargetBlocks = 512;
 
 // split-K of a reduced-precision Gram (128 x 128 tiles, lower triangle; k_split a multiple of 64)
@@ -291,7 +293,7 @@ void build_plan(Plan& p, Arena& a) {
     for (int n = 0; n < N; ++n) {
         p.U32[n] = a.take<float>(p.s[n] * p.R[n]);
         if (p.kind[n] == SMALL) p.Vsm[n] = a.take<double>(p.s[n] * p.s[n]);
-        p.U64[n] = a.take<double>(p.s[n] * p.R[n]);
+        p.U64[n] = a.take<double>(p.s[n] * p.Rc[n]);
     }
     const int64_t Xn = prod(p.s, 0, N);
     if (p.tree) {
@@ -359,6 +361,7 @@ void build_plan(Plan& p, Arena& a) {
     p.Q1 = a.take<double>(sR);
     p.W = a.take<double>(Rm * Rm);
     p.Wpart_elems = std::max<int64_t>(16 * Rm * Rm, 8 * sR);
+    if (Rm > 0 && Rm <= 1024) p.Wpart_elems = std::max(p.Wpart_elems, sym_eig_work_doubles((int)Rm));
     p.Wpart = a.take<double>(p.Wpart_elems);
     p.Tm = a.take<double>(Rm * Rm);
     p.chol_ws = a.take<int>(chol_counter_ints(Rm));
@@ -400,7 +403,7 @@ void build_plan(Plan& p, Arena& a) {
     }
     p.has_alt = p.tree && p.kind[0] == LARGE && p.kind[1] == LARGE;
     if (p.has_alt) {
-        const int64_t s0 = p.s[0], R0 = p.R[0];
+        const int64_t s0 = p.s[0], R0 = p.Rc[0];
         p.S64b = a.take<double>(s0 * s0);
         p.S64b_elems = s0 * s0;
         p.Zb = a.take<double>(s0 * R0);
@@ -450,6 +453,7 @@ struct Run {
     double orth_tol = 1e-12;    // CholeskyQR second-pass threshold on max |Q^T Q - I|
     int oi_steps_init = 0, oi_steps_sweeps = 0;   // orthogonal-iteration steps taken (host count)
     double oi_resid_max = 0.0;  // inner_tol > 0: largest final relative residual of an update
+    int rr_sweeps = 0;          // block-Jacobi sweeps of the Rayleigh-Ritz steps (oversampled starts)
 
     long long spin() const { return (long long)ctx->opt.wait_spin_limit; }
     double inner_tol() const { return ctx->opt.inner_tol; }
@@ -707,9 +711,9 @@ constexpr double kOrthTol = 1e-12;     // FP32 sweeps: the factors are orthonorm
 constexpr double kOrthTolLowp = 1e-8;  // reduced-precision sweeps: far below their 2^-8..2^-4 operands
 
 void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
-                    bool cold) {
+                    bool cold, bool mid = false) {
     Plan& p = r.p;
-    if (!cold && !U32) {
+    if (mid) {
         // an intermediate step of the cold start: one CholeskyQR pass gives a basis of span(Z),
         // all that the next product S U needs; the last step delivers the orthonormal factor
         gram_tn64(r, Z, z32, rows, cols, p.W, true);
@@ -745,7 +749,7 @@ void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols,
         apply_tri(r, U64, false, rows, cols, p.Tm, p.Q1);
         TK_HIP(hipMemcpyAsync(U64, p.Q1, rows * cols * sizeof(double), hipMemcpyDeviceToDevice, r.st));
     }
-    TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
+    if (U32) TK_HIP(f64_to_f32(U64, U32, rows * cols, r.st));
 }
 
 // ||Z - U (U^T Z)||_F for Z = S U in p.Z (s x R) and orthonormal U (FP64): the residual of span(U) as an
@@ -779,18 +783,14 @@ double subspace_residual(Run& r, const double* U, int64_t s, int64_t R) {
     return std::sqrt(e2);
 }
 
-// q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR.  With
-// inner_tol > 0, q is the most steps, and the iteration stops once span(U) is invariant to the
-// tolerance (checked once more after the q-th step)
-void orth_iter(Run& r, int n, int q, bool cold) {
+// Z = S U for the Gram S64 (s x s) and the basis U64[n] (s x cols), into p.Z.  The product has few
+// output tiles ((s/64) x (cols/64)); K is split so that the grid fills the chip, the FP64 partials
+// summed in a fixed order.  Split count: the best per-CU balance of workgroups (average over maximum
+// per CU), counting fewer than two per CU as under-filled; ties go to fewer splits (less partial-sum
+// traffic).
+void su_product(Run& r, int n, int64_t cols) {
     Plan& p = r.p;
-    const int64_t s = p.s[n], R = p.R[n];
-    if ((p.S64_elems > 0 && s * s > p.S64_elems) || (p.Z_elems > 0 && s * R > p.Z_elems) || R > p.chol_cap)
-        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "orthogonal-iteration scratch set too small for this mode"};
-    // Z = S U has few output tiles ((s/64) x (R/64)); K is split so that the grid fills the chip,
-    // the FP64 partials summed in a fixed order
-    // split count: the best per-CU balance of workgroups (average over maximum per CU), counting
-    // fewer than two per CU as under-filled; ties go to fewer splits (less partial-sum traffic)
+    const int64_t s = p.s[n], R = cols;
     const int64_t tiles = ((s + 63) / 64) * ((R + 63) / 64);
     const int64_t cus = device_cu_count();
     const int64_t maxsp = std::max<int64_t>(1, std::min<int64_t>(
@@ -808,6 +808,73 @@ void orth_iter(Run& r, int n, int q, bool cold) {
     int64_t ks = (s + splits - 1) / splits;
     ks = (ks + 15) / 16 * 16;
     const int nsplit = (int)((s + ks - 1) / ks);
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = s;
+    g.N = R;
+    g.K = s;
+    g.a = plain(p.S64, s);      // A(m, k) = S[k][m] (symmetric)
+    g.b = plain(p.U64[n], R);
+    if (nsplit > 1) {
+        g.k_split = ks;
+        g.c = plain(p.Wpart, R);
+        g.c_zstride = s * R;
+        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+        TK_HIP(tk_sum_splits_f64(p.Wpart, nsplit, s * R, s * R, p.Z, r.st));
+    } else {
+        g.c = plain(p.Z, R);
+        TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+    }
+}
+
+// Rayleigh-Ritz step closing an oversampled cold start (Rc = p.Rc[n] > R columns): with U (s x Rc,
+// orthonormal) in U64[n], B = U^T S U (Rc x Rc) is diagonalised in FP64 (block Jacobi) and the
+// factor becomes U V_R (s x R), V_R the eigenvectors of the R largest Ritz values, descending.  U V_R
+// is orthonormal to FP64 rounding (both factors are).  The eigensolver synchronises the stream once
+// per Jacobi sweep.
+void rayleigh_ritz(Run& r, int n) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n], R = p.R[n], Rc = p.Rc[n];
+    if (sym_eig_work_doubles((int)Rc) > p.Wpart_elems)
+        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Rayleigh-Ritz scratch too small"};
+    su_product(r, n, Rc);
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = Rc;
+    g.N = Rc;
+    g.K = s;
+    g.a = plain(p.U64[n], Rc);  // A(m, k) = U[k][m]
+    g.b = plain(p.Z, Rc);       // B(k, n) = (S U)[k][n]
+    g.c = plain(p.W, Rc);
+    g.k_split = s;
+    TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
+    int sweeps = 0;
+    TK_HIP(sym_eig_blocked(p.W, (int)Rc, (int)R, nullptr, p.Tm, nullptr, p.Wpart, r.st, &sweeps));
+    r.rr_sweeps += sweeps;
+    GemmArgs h{};
+    h.alpha = 1.0;
+    h.M = s;
+    h.N = R;
+    h.K = Rc;
+    h.a = plain(p.U64[n], Rc);  // A(m, k) = U[m][k]
+    h.b = plain(p.Tm, R);       // B(k, n) = V[k][n]
+    h.c = plain(p.Q1, R);
+    h.k_split = Rc;
+    TK_HIP(gemm_f64(h, MK, KM, EPI_STORE, false, false, r.st));
+    TK_HIP(hipMemcpyAsync(p.U64[n], p.Q1, s * R * sizeof(double), hipMemcpyDeviceToDevice, r.st));
+    TK_HIP(f64_to_f32(p.U64[n], p.U32[n], s * R, r.st));
+}
+
+// q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR.  With
+// inner_tol > 0, q is the most steps, and the iteration stops once span(U) is invariant to the
+// tolerance (checked once more after the q-th step).  An oversampled cold start iterates on p.Rc[n]
+// columns and ends with the Rayleigh-Ritz step.
+void orth_iter(Run& r, int n, int q, bool cold) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n], R = cold ? p.Rc[n] : p.R[n];
+    const bool ritz = cold && R > p.R[n];
+    if ((p.S64_elems > 0 && s * s > p.S64_elems) || (p.Z_elems > 0 && s * R > p.Z_elems) || R > p.chol_cap)
+        throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "orthogonal-iteration scratch set too small for this mode"};
     // inner_tol > 0: ||S||_F once; each step's product Z = S U first measures the residual of the
     // current U, and the iteration stops there when it is small enough
     const double tol = r.inner_tol();
@@ -819,35 +886,21 @@ void orth_iter(Run& r, int n, int q, bool cold) {
         snorm = std::sqrt(snorm);
     }
     for (int it = 0; it < q || (tol > 0.0 && it == q); ++it) {
-        GemmArgs g{};
-        g.alpha = 1.0;
-        g.M = s;
-        g.N = R;
-        g.K = s;
-        g.a = plain(p.S64, s);      // A(m, k) = S[k][m] (symmetric)
-        g.b = plain(p.U64[n], R);
-        if (nsplit > 1) {
-            g.k_split = ks;
-            g.c = plain(p.Wpart, R);
-            g.c_zstride = s * R;
-            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
-            TK_HIP(tk_sum_splits_f64(p.Wpart, nsplit, s * R, s * R, p.Z, r.st));
-        } else {
-            g.c = plain(p.Z, R);
-            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
-        }
+        su_product(r, n, R);
         if (tol > 0.0 && !(cold && it == 0)) {
             resid = subspace_residual(r, p.U64[n], s, R) / std::max(snorm, 1e-300);
             if (resid <= tol || it == q) break;
         }
         // cold start: shifted CholeskyQR3 for the first two steps, one pass for the intermediate
-        // ones (U32 = nullptr), the checked CholeskyQR2 for the last; with a tolerance every step
-        // may be the last, so every step after the first two is a checked CholeskyQR2
+        // ones, the checked CholeskyQR2 for the last; with a tolerance every step may be the last,
+        // so every step after the first two is a checked CholeskyQR2.  The FP32 copy is written
+        // only for a basis of the factor's own width.
         const bool mid = cold && it >= 2 && it < q - 1 && tol <= 0.0;
-        orthonormalize(r, p.Z, false, s, R, p.U64[n], mid ? nullptr : p.U32[n], cold && it < 2);
+        orthonormalize(r, p.Z, false, s, R, p.U64[n], ritz ? nullptr : p.U32[n], cold && it < 2, mid);
         (cold ? r.oi_steps_init : r.oi_steps_sweeps) += 1;
     }
     if (tol > 0.0) r.oi_resid_max = std::max(r.oi_resid_max, resid);
+    if (ritz) rayleigh_ritz(r, n);
 }
 
 // factor update of mode n from the Gram in S64
@@ -862,9 +915,11 @@ void update_factor(Run& r, int n, bool cold) {
         return;
     }
     if (cold) {
-        TK_HIP(fill_random(p.U32[n], p.s[n] * p.R[n], r.ctx->opt.seed * 0x100000001b3ull + (uint64_t)n * 0x9e3779b9ull,
+        // the seeded random start (s x Rc), drawn in FP32 into p.Q1 when it is wider than U32
+        float* u0 = p.Rc[n] > p.R[n] ? reinterpret_cast<float*>(p.Q1) : p.U32[n];
+        TK_HIP(fill_random(u0, p.s[n] * p.Rc[n], r.ctx->opt.seed * 0x100000001b3ull + (uint64_t)n * 0x9e3779b9ull,
                            r.st));
-        TK_HIP(f32_to_f64(p.U32[n], p.U64[n], p.s[n] * p.R[n], r.st));
+        TK_HIP(f32_to_f64(u0, p.U64[n], p.s[n] * p.Rc[n], r.st));
         orth_iter(r, n, std::max(1, r.ctx->opt.init_iters), true);
     } else {
         const int q = r.inner_override > 0 ? std::max(r.inner_override, r.ctx->opt.inner_iters) : r.ctx->opt.inner_iters;
@@ -1054,8 +1109,11 @@ void thosvd(Run& r) {
         }
     };
     lp_start_copy(r);
-    if (!p.has_alt || r.inner_tol() > 0.0) {
-        // (with a tolerance every step waits for the host, so the two streams could not overlap)
+    bool ritz = false;
+    for (int n = 0; n < p.N; ++n) ritz = ritz || p.Rc[n] > p.R[n];
+    if (!p.has_alt || r.inner_tol() > 0.0 || ritz) {
+        // (with a tolerance, or the Rayleigh-Ritz eigensolver, the host waits for the device inside
+        // a mode's start, so the two streams could not overlap)
         modes_from(0);
         return;
     }
@@ -1667,7 +1725,7 @@ tucker_status validate_args(int ndim, const int64_t* dims, const int64_t* ranks,
 }
 
 void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int max_iters, int prec = 0,
-               int refine = 0, bool pp = false) {
+               int refine = 0, bool pp = false, int oversample = 0) {
     p.N = ndim;
     p.max_iters = max_iters;
     p.refine = prec ? refine : 0;
@@ -1675,6 +1733,9 @@ void make_plan(Plan& p, int ndim, const int64_t* dims, const int64_t* ranks, int
         p.s[n] = dims[n];
         p.R[n] = ranks[n];
         p.kind[n] = (ranks[n] == dims[n]) ? FIXED : (dims[n] <= kSmallMode ? SMALL : LARGE);
+        p.Rc[n] = p.kind[n] == LARGE ? std::min<int64_t>(dims[n], ranks[n] + std::max(0, oversample)) : ranks[n];
+        if (p.Rc[n] > p.R[n] && p.Rc[n] > kRitzMaxOrder)
+            throw Fail{TUCKER_ERR_UNSUPPORTED, "oversampled start: min(s_n, R_n + oversample) exceeds 1024"};
     }
     p.tree = (ndim == 4) && pair_ttm_supported((int)dims[2], (int)dims[3]) && dims[2] * dims[3] <= 64;
     p.prec = prec;
@@ -1963,7 +2024,7 @@ tucker_status tucker_create(const tucker_options* opts, tucker_ctx** out) {
     if (opts) o = *opts;
     if (o.inner_iters < 1 || o.init_iters < 1 || o.refine_sweeps < 0 || o.precision < TUCKER_FP32 ||
         o.precision > TUCKER_FP8_E4M3 || o.device < 0 || !(o.inner_tol >= 0.0) || o.wait_spin_limit < 0 ||
-        !(o.pp_tol >= 0.0) ||
+        !(o.pp_tol >= 0.0) || o.oversample < 0 ||
         (o.start != TUCKER_START_THOSVD && o.start != TUCKER_START_STHOSVD))
         return TUCKER_ERR_INVALID_ARG;
     int count = 0;
@@ -2050,7 +2111,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         if (ctx->opt.pp_tol > 0.0 && tol > 0.0)
             throw Fail{TUCKER_ERR_UNSUPPORTED, "pairwise perturbation runs a fixed number of sweeps (tol = 0)"};
         make_plan(p, ndim, dims, ranks, max_iters, (int)ctx->opt.precision, ctx->opt.refine_sweeps,
-                  ctx->opt.pp_tol > 0.0);
+                  ctx->opt.pp_tol > 0.0, init_factors ? 0 : ctx->opt.oversample);
         bind(ctx, p);
         const hipStream_t s = r.st;
         reset_counters(r);
@@ -2229,6 +2290,7 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
         ctx->stats.oi_steps_init = r.oi_steps_init;
         ctx->stats.oi_steps_sweeps = r.oi_steps_sweeps;
         ctx->stats.oi_residual_max = r.oi_resid_max;
+        ctx->stats.rr_sweeps = r.rr_sweeps;
         ctx->stats.workspace_bytes = ctx->ws_bytes;
         if (!std::isfinite(fexact)) throw Fail{TUCKER_ERR_NUMERICAL, "non-finite fit"};
     });

@@ -6,8 +6,10 @@
 // blocks p and q exactly (cyclic Jacobi with the parallel round-robin ordering, Golub & Van Loan
 // Alg. 8.4.3, in LDS) and stores its rotation Q_pq; then A <- J^T A J and V <- V J, where J applies
 // each Q_pq to its two blocks, in two passes over the matrix (rows, then columns).  Sweeps repeat
-// until the off-diagonal mass is below 1e-30 of the total (in squares), checked on the host after each
-// sweep.  Padding rows and columns start decoupled (zero off-diagonal, a diagonal below every
+// until the off-diagonal mass is below np 2^-100 of the total (in squares), checked on the host after
+// each sweep: the sub-problems leave each off-diagonal pair below 2^-53 sqrt(|a_ii a_jj|), at most
+// np 2^-106 of the total in squares, so the test stops the sweeps once every pair is decoupled to
+// rounding (a factor 64 of margin).  Padding rows and columns start decoupled (zero off-diagonal, a diagonal below every
 // eigenvalue by Gershgorin's bound) and stay exactly decoupled, so the n largest diagonal entries at
 // the end are the eigenvalues.
 #include <algorithm>
@@ -84,12 +86,15 @@ __device__ __forceinline__ void slot_of(int T, int r, int blk, int& k, int& pos)
 
 // One workgroup per block pair: the 64 x 64 principal submatrix on blocks (p, q) is diagonalised by
 // cyclic Jacobi in LDS; Q (row-major 64 x 64, columns = eigenvectors of the submatrix) to Qbuf[k].
+// Threshold rule: the rotation of (i, j) is skipped when |a_ij| <= 2^-53 sqrt(|a_ii a_jj|) (the pair is
+// decoupled to the rounding of its diagonal), a round without rotations skips its updates, and the
+// sub-problem ends after a sweep without rotations.
 __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict__ Ap, int np, int T, int r,
                                                        double* __restrict__ Qbuf) {
     __shared__ double A[SP * SLD], Q[SP * SLD];
     __shared__ double cs[SP / 2], sn[SP / 2];
     __shared__ int pp_[SP / 2], qq_[SP / 2];
-    __shared__ double red[256];
+    __shared__ int rot[SP];
     const int tid = threadIdx.x;
     const int k = blockIdx.x;
     int bp, bq;
@@ -100,32 +105,10 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
         A[i * SLD + j] = Ap[(int64_t)grow(i) * np + grow(j)];
         Q[i * SLD + j] = (i == j) ? 1.0 : 0.0;
     }
-    __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int e = tid; e < SP * SP; e += 256) {
-            const int i = e / SP, j = e % SP;
-            const double v = A[i * SLD + j];
-            tot += v * v;
-            if (i != j) off += v * v;
-        }
-        red[tid] = off;
+        if (tid < SP) rot[tid] = 0;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        const double offs = red[0];
-        __syncthreads();
-        red[tid] = tot;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        const double tots = red[0];
-        __syncthreads();
-        if (!(offs > 1e-32 * tots)) break;
+        bool any = false;
         for (int rr = 0; rr < SP - 1; ++rr) {
             if (tid < SP / 2) {
                 auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + rr) % (SP - 1)); };
@@ -137,12 +120,13 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
                 }
                 double c = 1.0, s = 0.0;
                 const double apq = A[p * SLD + q];
-                if (apq != 0.0) {
-                    const double app = A[p * SLD + p], aqq = A[q * SLD + q];
+                const double app = A[p * SLD + p], aqq = A[q * SLD + q];
+                if (fabs(apq) > 0x1p-53 * sqrt(fabs(app) * fabs(aqq))) {
                     const double tau = (aqq - app) / (2.0 * apq);
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
                     s = t * c;
+                    rot[rr] = 1;
                 }
                 pp_[tid] = p;
                 qq_[tid] = q;
@@ -150,6 +134,8 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
                 sn[tid] = s;
             }
             __syncthreads();
+            if (rot[rr] == 0) continue;     // the same value in every thread: no barrier is skipped unevenly
+            any = true;
             for (int e = tid; e < (SP / 2) * SP; e += 256) {     // rows: A <- J^T A
                 const int kk = e / SP, col = e % SP;
                 const int p = pp_[kk], q = qq_[kk];
@@ -172,6 +158,7 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
             }
             __syncthreads();
         }
+        if (!any) break;
     }
     double* out = Qbuf + (int64_t)k * SP * SP;
     for (int e = tid; e < SP * SP; e += 256) out[e] = Q[(e / SP) * SLD + (e % SP)];
@@ -328,7 +315,7 @@ hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U
         e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        if (!(h[0] > 1e-30 * h[1])) break;
+        if (!(h[0] > (double)np * 0x1p-100 * h[1])) break;
         for (int rr = 0; rr < T - 1; ++rr) {
             hipLaunchKernelGGL(bj_solve_kernel, dim3(T / 2), dim3(256), 0, s, Ap, np, T, rr, Qbuf);
             hipLaunchKernelGGL(bj_rows_kernel, dim3(g2), dim3(256), 0, s, Ap, np, T, rr, Qbuf, tmp);

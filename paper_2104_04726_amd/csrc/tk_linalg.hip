@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) void finish_factor_kernel(const int* need, con
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const double v = second ? U64[i] : Q1[i];
         if (!second) U64[i] = v;
-        U32[i] = (float)v;
+        if (U32) U32[i] = (float)v;
     }
 }
 

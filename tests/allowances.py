@@ -55,6 +55,45 @@ def si_allowance(spectra, dims, ranks, steps=None, resid=None) -> float:
     return total
 
 
+def _ritz_bounds(lam, s, r, steps, oversample):
+    """Per-direction bounds on sin theta_i, i = 1..R, for orthogonal iteration on Rc = min(s, R + p)
+    columns followed by Rayleigh-Ritz (the R leading Ritz vectors of U^T S U).
+
+    The iteration leaves the i-th eigenvector at angle <= (lam_{Rc+1} / lam_i)^q sqrt(s Rc) from the
+    Rc-dimensional iterate (the subspace-iteration term above with Rc columns; 0 when Rc = s).  The
+    Ritz vectors taken from that subspace are off the eigenvectors by at most that angle times
+    sqrt(1 + gamma^2 / delta^2) (Saad, Numerical Methods for Large Eigenvalue Problems, Thm. 4.6),
+    with gamma = ||P S (I - P)|| <= lam_1 and delta >= lam_R - lam_{R+1} (Cauchy interlacing puts
+    every discarded Ritz value at or below lam_{R+1}), so the amplification is at most
+    sqrt(1 + g^2) with g = lam_1 / (lam_R - lam_{R+1}), the boundary gap factor."""
+    rc = min(s, r + oversample)
+    if rc >= s:
+        return np.zeros(r)
+    gap = lam[r - 1] - lam[r]
+    amp = math.sqrt(1.0 + (lam[0] / gap) ** 2) if gap > 0 else math.inf
+    cont = (lam[rc] / lam[:r]) ** steps * math.sqrt(s * rc)
+    return np.minimum(1.0, cont * amp)
+
+
+def rr_allowance(spectra, dims, ranks, steps, oversample) -> float:
+    """sum_n a_n as in si_allowance, for the oversampled start closed by Rayleigh-Ritz."""
+    total = 0.0
+    for n, (s, r) in enumerate(zip(dims, ranks)):
+        if r >= s or s <= SMALL_MODE:
+            continue
+        lam = np.maximum(np.asarray(spectra[n], dtype=np.float64), 0.0)
+        t = _ritz_bounds(lam, s, r, steps, oversample)
+        total += math.sqrt(2.0 * float(np.sum(lam[:r] * t * t)) / float(np.sum(lam)))
+    return total
+
+
+def rr_sine_bound(spectrum, s, r, steps, oversample) -> float:
+    """Bound on the largest principal-angle sine between the R-dimensional result of the oversampled
+    start and the leading eigenspace (the boundary direction's term of _ritz_bounds)."""
+    lam = np.maximum(np.asarray(spectrum, dtype=np.float64), 0.0)
+    return float(_ritz_bounds(lam, s, r, steps, oversample)[-1])
+
+
 def pair_allowance(spectra, ranks, gap_limit=1e8) -> float:
     """One boundary direction pair, sqrt(2 lam_R / sum(lam)), for every mode whose boundary gap
     factor lam_1 / (lam_R - lam_{R+1}) exceeds gap_limit (a degenerate boundary)."""

@@ -97,6 +97,20 @@ def test_create_without_gpu_reports_device_error():
     assert not h.value
 
 
+def test_invalid_options_are_rejected_before_the_device():
+    """Option checks run on the host before any device call: a negative oversampling (or step
+    count) is an argument error whether or not a GPU is present."""
+    lib = _lib.lib()
+    for field, value in (("oversample", -1), ("init_iters", 0), ("pp_tol", -1.0)):
+        o = _lib.Options()
+        lib.tucker_default_options(C.byref(o))
+        assert o.oversample == 0
+        setattr(o, field, value)
+        h = C.c_void_p()
+        assert lib.tucker_create(C.byref(o), C.byref(h)) == _lib.ERR_INVALID_ARG, field
+        assert not h.value
+
+
 def test_server_without_gpu_and_null_arguments():
     import torch
     lib = _lib.lib()
