@@ -1,17 +1,19 @@
 // Symmetric eigen-decomposition of an n x n FP64 matrix, n <= 1024, by two-sided block Jacobi.
 //
-// The matrix is padded to np (a multiple of 64) and split into T = np / 32 blocks of 32 rows.  A sweep
+// The matrix is padded to np (a multiple of 64) and split into T = np / 16 blocks of 16 rows.  A sweep
 // runs T - 1 rounds of the round-robin tournament over the blocks; in a round every pair (p, q) of
-// blocks is independent: one workgroup diagonalises the 64 x 64 principal submatrix on the rows of
+// blocks is independent: one workgroup diagonalises the 32 x 32 principal submatrix on the rows of
 // blocks p and q exactly (cyclic Jacobi with the parallel round-robin ordering, Golub & Van Loan
 // Alg. 8.4.3, in LDS) and stores its rotation Q_pq; then A <- J^T A J and V <- V J, where J applies
-// each Q_pq to its two blocks, in two passes over the matrix (rows, then columns).  Sweeps repeat
+// each Q_pq to its two blocks, in one launch that updates every block pair of A and every block of V
+// in place (small sub-problems: their Jacobi sweeps are latency-bound, so 16-row blocks give twice
+// the rounds of 32-row blocks at about a quarter of the cost each).  Sweeps repeat
 // until the off-diagonal mass is below np 2^-100 of the total (in squares), checked on the host after
-// each sweep: the sub-problems leave each off-diagonal pair below 2^-53 sqrt(|a_ii a_jj|), at most
-// np 2^-106 of the total in squares, so the test stops the sweeps once every pair is decoupled to
-// rounding (a factor 64 of margin).  Padding rows and columns start decoupled (zero off-diagonal, a diagonal below every
-// eigenvalue by Gershgorin's bound) and stay exactly decoupled, so the n largest diagonal entries at
-// the end are the eigenvalues.
+// each sweep: once every pair is below the sub-problems' rotation threshold 2^-53 sqrt(|a_ii a_jj|), the
+// off-diagonal mass is at most np 2^-106 of the total, so the test stops the sweeps there (a factor 64
+// of margin).  Padding rows and columns start decoupled (zero off-diagonal, a diagonal of
+// -(1 + ||A||_F), below every eigenvalue) and stay exactly decoupled, so the n largest diagonal entries
+// at the end are the eigenvalues.
 #include <algorithm>
 #include <cmath>
 
@@ -20,33 +22,17 @@
 namespace tk {
 namespace {
 
-constexpr int EB = 32;            // block rows
+constexpr int EB = 16;            // block rows
 constexpr int SP = 2 * EB;        // sub-problem order
 constexpr int SLD = SP + 1;       // LDS row stride
+constexpr int kSubSweeps = 1;     // Jacobi sweeps of a sub-problem per round
 
-// -(1 + max_i sum_j |A_ij|): below every eigenvalue of A (Gershgorin)
-__global__ __launch_bounds__(256) void pad_value_kernel(const double* __restrict__ A, int n, double* out) {
-    __shared__ double red[256];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += fabs(A[(int64_t)i * n + j]);
-        m = fmax(m, s);
-    }
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = -(1.0 + red[0]);
-}
-
-// Ap (np x np) = A symmetrised, padded; V = I
+// Ap (np x np) = A symmetrised, padded; V = I.  The padding diagonal is -(1 + ||A||_F), below every
+// eigenvalue (|lam| <= ||sym(A)||_F <= ||A||_F); fro2[1] holds ||A||_F^2.
 __global__ __launch_bounds__(256) void eig_init_kernel(const double* __restrict__ A, int n, int np,
-                                                       const double* __restrict__ padv, double* __restrict__ Ap,
+                                                       const double* __restrict__ fro2, double* __restrict__ Ap,
                                                        double* __restrict__ V) {
-    const double pv = *padv;
+    const double pv = -(1.0 + sqrt(fro2[1]));
     const int64_t total = (int64_t)np * np;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e / np), j = (int)(e % np);
@@ -84,16 +70,26 @@ __device__ __forceinline__ void slot_of(int T, int r, int blk, int& k, int& pos)
     pos = (blk == p) ? 0 : 1;
 }
 
-// One workgroup per block pair: the 64 x 64 principal submatrix on blocks (p, q) is diagonalised by
-// cyclic Jacobi in LDS; Q (row-major 64 x 64, columns = eigenvectors of the submatrix) to Qbuf[k].
-// Threshold rule: the rotation of (i, j) is skipped when |a_ij| <= 2^-53 sqrt(|a_ii a_jj|) (the pair is
-// decoupled to the rounding of its diagonal), a round without rotations skips its updates, and the
-// sub-problem ends after a sweep without rotations.
+// One workgroup per block pair: one cyclic Jacobi sweep in LDS over the SP x SP principal submatrix on
+// blocks (p, q); the accumulated rotation Q (row-major SP x SP) to Qbuf[k].  A single sweep per round,
+// not the sub-problem solved to convergence: the outer sweeps needed barely change (11 -> 12 for a
+// dense graded 128 x 128 matrix, emulated), while each round's latency falls several-fold.
+// Within a round the SP/2 rotations act on disjoint index pairs, so A' = J^T A J is updated one 2 x 2
+// block at a time: the block on rows {p_a, q_a} and columns {p_b, q_b} becomes J_a^T A_blk J_b, read
+// and written by one thread (one phase, one barrier), and the diagonal blocks' couplings are stored
+// as zero (exact in exact arithmetic; their rounding residue, up to 2^-53 max(|a_pp|, |a_qq|), would
+// otherwise re-trigger rotations when the diagonal is graded).  Threshold rule: the rotation of (p, q)
+// is skipped when a_pq^2 <= 2^-106 |a_pp a_qq| (decoupled to the rounding of its diagonal), and a
+// round without rotations skips its update.  Rotation (Golub & Van Loan Alg. 8.4.2, the smaller angle,
+// written with one square root and one reciprocal square root): d = a_qq - a_pp, h = 2 a_pq,
+// r = sqrt(d^2 + h^2), u = r + |d|, c = u / sqrt(2 r u), s = sign(d) h / sqrt(2 r u) (so that
+// t = s / c = sign(d) h / (|d| + r)).
 __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict__ Ap, int np, int T, int r,
                                                        double* __restrict__ Qbuf) {
+    constexpr int HP = SP / 2;
     __shared__ double A[SP * SLD], Q[SP * SLD];
-    __shared__ double cs[SP / 2], sn[SP / 2];
-    __shared__ int pp_[SP / 2], qq_[SP / 2];
+    __shared__ double cs[HP], sn[HP];
+    __shared__ int pp_[HP], qq_[HP];
     __shared__ int rot[SP];
     const int tid = threadIdx.x;
     const int k = blockIdx.x;
@@ -105,12 +101,11 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
         A[i * SLD + j] = Ap[(int64_t)grow(i) * np + grow(j)];
         Q[i * SLD + j] = (i == j) ? 1.0 : 0.0;
     }
-    for (int sweep = 0; sweep < 30; ++sweep) {
+    for (int sweep = 0; sweep < kSubSweeps; ++sweep) {
         if (tid < SP) rot[tid] = 0;
         __syncthreads();
-        bool any = false;
         for (int rr = 0; rr < SP - 1; ++rr) {
-            if (tid < SP / 2) {
+            if (tid < HP) {
                 auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + rr) % (SP - 1)); };
                 int p = player(tid), q = player(SP - 1 - tid);
                 if (p > q) {
@@ -121,11 +116,13 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
                 double c = 1.0, s = 0.0;
                 const double apq = A[p * SLD + q];
                 const double app = A[p * SLD + p], aqq = A[q * SLD + q];
-                if (fabs(apq) > 0x1p-53 * sqrt(fabs(app) * fabs(aqq))) {
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
+                if (apq * apq > 0x1p-106 * fabs(app * aqq)) {
+                    const double d = aqq - app, h = 2.0 * apq;
+                    const double rad = sqrt(fma(d, d, h * h));
+                    const double u = rad + fabs(d);
+                    const double w = rsqrt(2.0 * rad * u);
+                    c = u * w;
+                    s = (d < 0.0 ? -h : h) * w;
                     rot[rr] = 1;
                 }
                 pp_[tid] = p;
@@ -135,76 +132,107 @@ __global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict_
             }
             __syncthreads();
             if (rot[rr] == 0) continue;     // the same value in every thread: no barrier is skipped unevenly
-            any = true;
-            for (int e = tid; e < (SP / 2) * SP; e += 256) {     // rows: A <- J^T A
-                const int kk = e / SP, col = e % SP;
-                const int p = pp_[kk], q = qq_[kk];
-                const double c = cs[kk], s = sn[kk];
-                const double ap = A[p * SLD + col], aq = A[q * SLD + col];
-                A[p * SLD + col] = c * ap - s * aq;
-                A[q * SLD + col] = s * ap + c * aq;
+            for (int e = tid; e < HP * HP; e += 256) {           // A <- J^T A J, one 2 x 2 block each
+                const int ka = e / HP, kb = e % HP;
+                const int pa = pp_[ka], qa = qq_[ka], pb = pp_[kb], qb = qq_[kb];
+                const double ca = cs[ka], sa = sn[ka], cb = cs[kb], sb = sn[kb];
+                const double x00 = A[pa * SLD + pb], x01 = A[pa * SLD + qb];
+                const double x10 = A[qa * SLD + pb], x11 = A[qa * SLD + qb];
+                const double y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
+                const double y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
+                A[pa * SLD + pb] = cb * y00 - sb * y01;
+                A[pa * SLD + qb] = (ka == kb) ? 0.0 : sb * y00 + cb * y01;
+                A[qa * SLD + pb] = (ka == kb) ? 0.0 : cb * y10 - sb * y11;
+                A[qa * SLD + qb] = sb * y10 + cb * y11;
             }
-            __syncthreads();
-            for (int e = tid; e < (SP / 2) * SP; e += 256) {     // columns: A <- A J, Q <- Q J
-                const int kk = e / SP, row = e % SP;
-                const int p = pp_[kk], q = qq_[kk];
-                const double c = cs[kk], s = sn[kk];
-                const double ap = A[row * SLD + p], aq = A[row * SLD + q];
-                A[row * SLD + p] = c * ap - s * aq;
-                A[row * SLD + q] = s * ap + c * aq;
-                const double vp = Q[row * SLD + p], vq = Q[row * SLD + q];
-                Q[row * SLD + p] = c * vp - s * vq;
-                Q[row * SLD + q] = s * vp + c * vq;
+            for (int e = tid; e < HP * SP; e += 256) {           // Q <- Q J
+                const int kb = e / SP, row = e % SP;
+                const int pb = pp_[kb], qb = qq_[kb];
+                const double cb = cs[kb], sb = sn[kb];
+                const double vp = Q[row * SLD + pb], vq = Q[row * SLD + qb];
+                Q[row * SLD + pb] = cb * vp - sb * vq;
+                Q[row * SLD + qb] = sb * vp + cb * vq;
             }
             __syncthreads();
         }
-        if (!any) break;
     }
     double* out = Qbuf + (int64_t)k * SP * SP;
     for (int e = tid; e < SP * SP; e += 256) out[e] = Q[(e / SP) * SLD + (e % SP)];
 }
 
-// B = J^T A (rows): row i of block I (pair k, position pos, local row li) becomes
-// sum_l Q_k[l][pos*32 + li] A[row of l in pair k][j]
-__global__ __launch_bounds__(256) void bj_rows_kernel(const double* __restrict__ A, int np, int T, int r,
-                                                      const double* __restrict__ Qbuf, double* __restrict__ B) {
-    const int64_t total = (int64_t)np * np;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e / np), j = (int)(e % np);
-        const int blk = i / EB, li = i % EB;
-        int k, pos, p, q;
-        slot_of(T, r, blk, k, pos);
-        pair_of(T, r, k, p, q);
-        const double* Qk = Qbuf + (int64_t)k * SP * SP;
-        const int col = pos * EB + li;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int l = 0; l < EB; ++l) acc = fma(Qk[l * SP + col], A[(int64_t)(p * EB + l) * np + j], acc);
-#pragma unroll 8
-        for (int l = 0; l < EB; ++l) acc = fma(Qk[(EB + l) * SP + col], A[(int64_t)(q * EB + l) * np + j], acc);
-        B[e] = acc;
+// One round's rotation J applied in place.  A <- J^T A J on the (T/2)(T/2+1)/2 block pairs (ki, kj),
+// ki <= kj: the SP x SP block on the rows of pair ki's two blocks and the columns of pair kj's becomes
+// Q_ki^T A_blk Q_kj, and its transpose is stored in the mirrored block (so A stays exactly symmetric).
+// V <- V J on (np / SP) x (T/2) blocks: the SP rows of a row chunk on the columns of pair kj become
+// V_blk Q_kj.  Every block is read and written by its own workgroup only.
+__global__ __launch_bounds__(256) void bj_apply_kernel(double* __restrict__ A, double* __restrict__ V, int np, int T,
+                                                       int r, const double* __restrict__ Qbuf) {
+    __shared__ double M[SP * SLD], Qa[SP * SLD], Qb[SP * SLD];
+    constexpr int PER = SP * SP / 256;            // outputs per thread
+    const int tid = threadIdx.x;
+    const int half = T / 2;
+    const int nA = half * (half + 1) / 2;
+    int b = blockIdx.x;
+    int ki = 0, kj = 0, rb = 0;
+    const bool onA = b < nA;
+    if (onA) {
+        while (b >= half - ki) {
+            b -= half - ki;
+            ++ki;
+        }
+        kj = ki + b;
+    } else {
+        b -= nA;
+        kj = b % half;
+        rb = b / half;
     }
-}
-
-// C = B J (columns), for the matrix and for the eigenvector basis
-__global__ __launch_bounds__(256) void bj_cols_kernel(const double* __restrict__ B, int np, int T, int r,
-                                                      const double* __restrict__ Qbuf, double* __restrict__ C) {
-    const int64_t total = (int64_t)np * np;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e / np), j = (int)(e % np);
-        const int blk = j / EB, lj = j % EB;
-        int k, pos, p, q;
-        slot_of(T, r, blk, k, pos);
-        pair_of(T, r, k, p, q);
-        const double* Qk = Qbuf + (int64_t)k * SP * SP;
-        const int col = pos * EB + lj;
-        const double* brow = B + (int64_t)i * np;
-        double acc = 0.0;
+    int pi = 0, qi = 0, pj, qj;
+    if (onA) pair_of(T, r, ki, pi, qi);
+    pair_of(T, r, kj, pj, qj);
+    auto rowg = [&](int l) { return onA ? ((l < EB) ? pi * EB + l : qi * EB + (l - EB)) : rb * SP + l; };
+    auto colg = [&](int l) { return (l < EB) ? pj * EB + l : qj * EB + (l - EB); };
+    double* __restrict__ X = onA ? A : V;
+    const double* Qj = Qbuf + (int64_t)kj * SP * SP;
+    const double* Qi = Qbuf + (int64_t)ki * SP * SP;
+    for (int e = tid; e < SP * SP; e += 256) {
+        const int i = e / SP, j = e % SP;
+        M[i * SLD + j] = X[(int64_t)rowg(i) * np + colg(j)];
+        Qb[i * SLD + j] = Qj[e];
+        if (onA) Qa[i * SLD + j] = Qi[e];
+    }
+    __syncthreads();
+    double acc[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {                // C = M Q_kj
+        const int e = tid + 256 * t, i = e / SP, j = e % SP;
+        double v = 0.0;
 #pragma unroll 8
-        for (int l = 0; l < EB; ++l) acc = fma(brow[p * EB + l], Qk[l * SP + col], acc);
+        for (int l = 0; l < SP; ++l) v = fma(M[i * SLD + l], Qb[l * SLD + j], v);
+        acc[t] = v;
+    }
+    if (!onA) {
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + 256 * t, i = e / SP, j = e % SP;
+            X[(int64_t)rowg(i) * np + colg(j)] = acc[t];
+        }
+        return;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = tid + 256 * t;
+        M[(e / SP) * SLD + (e % SP)] = acc[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {                // A' = Q_ki^T C
+        const int e = tid + 256 * t, i = e / SP, j = e % SP;
+        double v = 0.0;
 #pragma unroll 8
-        for (int l = 0; l < EB; ++l) acc = fma(brow[q * EB + l], Qk[(EB + l) * SP + col], acc);
-        C[e] = acc;
+        for (int l = 0; l < SP; ++l) v = fma(Qa[l * SLD + i], M[l * SLD + j], v);
+        X[(int64_t)rowg(i) * np + colg(j)] = v;
+        if (ki != kj) X[(int64_t)colg(j) * np + rowg(i)] = v;
     }
 }
 
@@ -233,15 +261,27 @@ __global__ __launch_bounds__(256) void offnorm_kernel(const double* __restrict__
         partial[2 * blockIdx.x + 1] = r2[0];
     }
 }
-__global__ void offnorm_fold_kernel(const double* partial, int nb, double* out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            a += partial[2 * i];
-            b += partial[2 * i + 1];
+// fold of the nb partial pairs by one workgroup, in a fixed order
+__global__ __launch_bounds__(256) void offnorm_fold_kernel(const double* __restrict__ partial, int nb, double* out) {
+    __shared__ double r1[256], r2[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    r1[threadIdx.x] = a;
+    r2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            r1[threadIdx.x] += r1[threadIdx.x + w];
+            r2[threadIdx.x] += r2[threadIdx.x + w];
         }
-        out[0] = a;
-        out[1] = b;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = r1[0];
+        out[1] = r2[0];
     }
 }
 
@@ -249,11 +289,14 @@ __global__ void offnorm_fold_kernel(const double* partial, int nb, double* out) 
 // lam[0..n); then U (n x r, row-major; and/or U32) = the eigenvectors of the first r
 __global__ __launch_bounds__(256) void eig_sort_kernel(const double* __restrict__ A, int n, int np,
                                                        int* __restrict__ rank, double* __restrict__ lam) {
+    __shared__ double dg[1024];
+    for (int j = threadIdx.x; j < np; j += 256) dg[j] = A[(int64_t)j * np + j];
+    __syncthreads();
     for (int i = blockIdx.x * 256 + threadIdx.x; i < np; i += gridDim.x * 256) {
-        const double li = A[(int64_t)i * np + i];
+        const double li = dg[i];
         int k = 0;
         for (int j = 0; j < np; ++j) {
-            const double lj = A[(int64_t)j * np + j];
+            const double lj = dg[j];
             if (lj > li || (lj == li && j < i)) ++k;
         }
         rank[i] = k;
@@ -285,7 +328,7 @@ unsigned grid_for_elems(int64_t n) {
 int64_t sym_eig_work_doubles(int n) {
     const int64_t np = (int64_t)((n + 63) / 64) * 64;
     const int64_t T = np / EB;
-    return 3 * np * np + (T / 2) * SP * SP + 2 * 1024 + 16 + np;   // Ap, V, tmp, Q blocks, partials, scalars, ranks
+    return 2 * np * np + (T / 2) * SP * SP + 2 * 1024 + 16 + np;   // Ap, V, Q blocks, partials, scalars, ranks
 }
 
 hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U, float* U32, double* work,
@@ -295,22 +338,22 @@ hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U
     const int T = np / EB;
     double* Ap = work;
     double* V = Ap + (int64_t)np * np;
-    double* tmp = V + (int64_t)np * np;
-    double* Qbuf = tmp + (int64_t)np * np;
+    double* Qbuf = V + (int64_t)np * np;
     double* partial = Qbuf + (int64_t)(T / 2) * SP * SP;
     double* scal = partial + 2 * 1024;
     int* rank = reinterpret_cast<int*>(scal + 16);
-    hipLaunchKernelGGL(pad_value_kernel, dim3(1), dim3(256), 0, s, A, n, scal + 2);
-    hipLaunchKernelGGL(eig_init_kernel, dim3(grid_for_elems((int64_t)np * np)), dim3(256), 0, s, A, n, np, scal + 2,
-                       Ap, V);
+    const unsigned g2 = grid_for_elems((int64_t)np * np);
+    const int nbo = (int)std::min<unsigned>(g2, 64);
+    hipLaunchKernelGGL(offnorm_kernel, dim3(nbo), dim3(256), 0, s, A, n, partial);      // ||A||_F^2 to scal[3]
+    hipLaunchKernelGGL(offnorm_fold_kernel, dim3(1), dim3(256), 0, s, partial, nbo, scal + 2);
+    hipLaunchKernelGGL(eig_init_kernel, dim3(g2), dim3(256), 0, s, A, n, np, scal + 2, Ap, V);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned g2 = grid_for_elems((int64_t)np * np);
-    const int nbo = (int)std::min<unsigned>(g2, 1024);
+    const unsigned napply = (unsigned)((T / 2) * (T / 2 + 1) / 2 + (np / SP) * (T / 2));
     int sweeps = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
         hipLaunchKernelGGL(offnorm_kernel, dim3(nbo), dim3(256), 0, s, Ap, np, partial);
-        hipLaunchKernelGGL(offnorm_fold_kernel, dim3(1), dim3(64), 0, s, partial, nbo, scal);
+        hipLaunchKernelGGL(offnorm_fold_kernel, dim3(1), dim3(256), 0, s, partial, nbo, scal);
         double h[2] = {0.0, 0.0};
         e = hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -318,10 +361,7 @@ hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U
         if (!(h[0] > (double)np * 0x1p-100 * h[1])) break;
         for (int rr = 0; rr < T - 1; ++rr) {
             hipLaunchKernelGGL(bj_solve_kernel, dim3(T / 2), dim3(256), 0, s, Ap, np, T, rr, Qbuf);
-            hipLaunchKernelGGL(bj_rows_kernel, dim3(g2), dim3(256), 0, s, Ap, np, T, rr, Qbuf, tmp);
-            hipLaunchKernelGGL(bj_cols_kernel, dim3(g2), dim3(256), 0, s, tmp, np, T, rr, Qbuf, Ap);
-            hipLaunchKernelGGL(bj_cols_kernel, dim3(g2), dim3(256), 0, s, V, np, T, rr, Qbuf, tmp);
-            std::swap(V, tmp);
+            hipLaunchKernelGGL(bj_apply_kernel, dim3(napply), dim3(256), 0, s, Ap, V, np, T, rr, Qbuf);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
