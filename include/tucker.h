@@ -99,7 +99,10 @@ typedef struct {
                                     the sweeps are launched one kernel at a time)              */
     size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
     uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
-    int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats)   */
+    int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats).
+                                    Each timed stage records two events on the stream, and each
+                                    costs the device a few microseconds of idle time between
+                                    kernels, so timing slows a sweep by up to about 10%        */
     int64_t wait_spin_limit;     /* bound of every wait inside the Cholesky task graph, in sleep
                                     steps of about 64 cycles; 0 = the default (2^24, about half
                                     a second).  A wait that reaches it gives up, the kernel
@@ -122,6 +125,8 @@ typedef struct {
                                     exact.  FP32 sweeps (tol = 0) of order-4 stacks whose third
                                     mode is kept at full rank (identity factor) only, else
                                     TUCKER_ERR_UNSUPPORTED.  0 (default): ordinary sweeps.        */
+    uint32_t timing_stages;      /* timing = 1: bit s set times stage s (tucker_stage) only;
+                                    0 (default) times every stage                              */
     int oversample;              /* p >= 0: the cold start of a large mode (T-HOSVD or ST-HOSVD
                                     start) iterates on Rc = min(s_n, R_n + p) columns and ends with
                                     a Rayleigh-Ritz step: B = U^T S U (Rc x Rc) is diagonalised in
@@ -453,6 +458,9 @@ tucker_status tucker_autotune_force(int op, int choice);
 const char* tucker_status_string(tucker_status s);
 const char* tucker_last_error(const tucker_ctx* ctx);   /* never NULL; "" when none */
 tucker_status tucker_get_stats(const tucker_ctx* ctx, tucker_stats* out);
+/* Changes tucker_options.timing and .timing_stages of a context for its later calls (host only,
+ * no allocation).  TUCKER_ERR_INVALID_ARG for a NULL context or timing not 0 or 1. */
+tucker_status tucker_set_timing(tucker_ctx* ctx, int timing, uint32_t stages);
 
 #ifdef __cplusplus
 }

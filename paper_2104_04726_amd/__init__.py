@@ -85,7 +85,7 @@ class Context:
                  seed: int = 0x5EED, hbm_budget_bytes: int = 0, precision: str = "fp32",
                  refine_sweeps: int = 1, timing: bool = False, use_graphs: bool = False, inner_tol: float = 0.0,
                  wait_spin_limit: int = 0, start: str = "thosvd", autotune: bool = False, pp_tol: float = 0.0,
-                 oversample: int = 0):
+                 oversample: int = 0, timing_stages=None):
         import torch
         lib = _lib.lib()
         opts = _lib.Options()
@@ -109,6 +109,7 @@ class Context:
         opts.autotune = 1 if autotune else 0
         opts.pp_tol = float(pp_tol)
         opts.oversample = int(oversample)
+        opts.timing_stages = sum(1 << _lib.STAGES.index(n) for n in (timing_stages or ()))
         self.device = int(device)
         self._h = C.c_void_p()
         _check(lib.tucker_create(C.byref(opts), C.byref(self._h)))
@@ -309,6 +310,13 @@ class Context:
         out = C.c_double(0.0)
         _check(_lib.lib().tucker_sumsq(self._h, C.c_void_p(x.data_ptr()), int(x.numel()), C.byref(out)), self._h)
         return float(out.value)
+
+    def set_timing(self, on: bool, stages=None):
+        """Stage timing of later calls: every stage (stages None), or only the named ones."""
+        mask = 0
+        for name in stages or ():
+            mask |= 1 << _lib.STAGES.index(name)
+        _check(_lib.lib().tucker_set_timing(self._h, 1 if on else 0, mask), self._h)
 
     def stats(self) -> dict:
         st = _lib.Stats()

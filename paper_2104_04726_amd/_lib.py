@@ -36,6 +36,7 @@ class Options(C.Structure):
         ("start", C.c_int),
         ("autotune", C.c_int),
         ("pp_tol", C.c_double),
+        ("timing_stages", C.c_uint32),
         ("oversample", C.c_int),
     ]
 
@@ -159,6 +160,7 @@ def _declare(lib):
     lib.tucker_chol_inv_noalloc.argtypes = [v, v, C.c_int64, v]
     lib.tucker_sym_eig.argtypes = [v, v, C.c_int64, C.c_int64, v, v]
     lib.tucker_sumsq.argtypes = [v, v, C.c_int64, C.POINTER(C.c_double)]
+    lib.tucker_set_timing.argtypes = [v, C.c_int, C.c_uint32]
     lib.tucker_autotune_dump.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.tucker_autotune_dump.restype = C.c_int
     lib.tucker_autotune_clear.argtypes = []

@@ -475,7 +475,8 @@ struct StageTimer {
     int stage;
     int b = -1;
     StageTimer(Run& run, int s) : r(run), stage(s) {
-        if (r.ctx->opt.timing && stage >= 0) b = r.record();
+        const uint32_t mask = r.ctx->opt.timing_stages;
+        if (r.ctx->opt.timing && stage >= 0 && (mask == 0 || ((mask >> stage) & 1u))) b = r.record();
     }
     ~StageTimer() {
         if (b >= 0) {
@@ -2736,6 +2737,13 @@ const char* tucker_last_error(const tucker_ctx* ctx) { return ctx ? ctx->err.c_s
 tucker_status tucker_get_stats(const tucker_ctx* ctx, tucker_stats* out) {
     if (!ctx || !out) return TUCKER_ERR_INVALID_ARG;
     *out = ctx->stats;
+    return TUCKER_OK;
+}
+
+tucker_status tucker_set_timing(tucker_ctx* ctx, int timing, uint32_t stages) {
+    if (!ctx || (timing != 0 && timing != 1)) return TUCKER_ERR_INVALID_ARG;
+    ctx->opt.timing = timing;
+    ctx->opt.timing_stages = stages;
     return TUCKER_OK;
 }
 

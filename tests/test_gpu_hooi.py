@@ -276,6 +276,31 @@ def test_deterministic(ctx):
     assert np.array_equal(a.core.cpu().numpy(), b.core.cpu().numpy())
 
 
+def test_stage_timing_selection():
+    """timing_stages (and tucker_set_timing) restrict the HIP-event stage timers to the named stages;
+    timing changes no result."""
+    import paper_2104_04726_amd as tk
+    c = STACK_CONFIGS["stack_mini"]
+    x32 = make_stereo_stack(c["H"], c["W"], c["E"], c["colorspace"], c["seed"])
+    ranks = c["ranks"]
+    _say("stage timing selection")
+    ctx2 = tk.Context(0, timing=True, timing_stages=["pass_c1"])
+    try:
+        a = ctx2.decompose(_dev(x32), ranks, 3)
+        assert set(a.stats["stages"]) == {"pass_c1"} and a.stats["stages"]["pass_c1"][1] == 3
+        ctx2.set_timing(True)
+        b = ctx2.decompose(_dev(x32), ranks, 3)
+        assert {"pass_a", "pass_c1", "ttm_c2", "core"} <= set(b.stats["stages"])
+        ctx2.set_timing(False)
+        c3 = ctx2.decompose(_dev(x32), ranks, 3)
+        assert not c3.stats["stages"]
+    finally:
+        ctx2.close()
+    for r in (b, c3):
+        assert r.fit == a.fit
+        assert np.array_equal(r.core.cpu().numpy(), a.core.cpu().numpy())
+
+
 def test_zero_and_nonfinite_inputs(ctx):
     import paper_2104_04726_amd as tk
     _say("zero / nan")
