@@ -34,6 +34,8 @@ using namespace tk;
 
 hipError_t tk_sum_splits_f64(const double* P, int nsplit, int64_t n, int64_t zstride, double* out, hipStream_t s);
 hipError_t tk_sum_splits_to_f32(const double* P, int nsplit, int64_t n, int64_t zstride, float* out, hipStream_t s);
+template <typename TO>
+hipError_t tk_sum_splits_f32p(const float* P, int nsplit, int64_t n, int64_t zstride, TO* out, hipStream_t s);
 hipError_t tk_set_int(int* p, int v, hipStream_t s);
 hipError_t tk_fit_push(const double* src, int* counter, double* fits, hipStream_t s);
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
@@ -234,6 +236,7 @@ constexpr double kGramSplitOverheadK = 256.0;   // fixed cost of a workgroup, in
 constexpr int kLpScaleBlocks = 256;
 constexpr int kRefineInner = 4;
 constexpr int64_t kRitzMaxOrder = 1024;   // largest Rayleigh-Ritz matrix (block-Jacobi eigensolver)
+constexpr int64_t kZSplitK = 128;         // longest FP32-accumulated k range of the one-step S U product
 constexpr int kLpGramTargetBlocks = 512;
 
 // split-K of a reduced-precision Gram (128 x 128 tiles, lower triangle; k_split a multiple of 64)
@@ -956,8 +959,13 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
     const int64_t R = p.R[n], AB = A * B;
     if (wp.R * wp.N > 2 * p.P_elems) throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "direct update buffer too small"};
     float* W = (float*)p.P;
+    float* part = reinterpret_cast<float*>(p.Wpart);     // FP32 split partials (2 per FP64 slot)
+    const int64_t part_cap = 2 * p.Wpart_elems;
     {
         StageTimer t(r, stage_prod);
+        // W = U^T Y on the FP32 matrix cores, accumulated in FP32 over K = s_n like the products that
+        // formed Y (their rounding, up to K u, bounds what W can carry); K split in two, FP32 partials
+        // summed in FP64 and rounded once, when the output tiles alone leave the CUs unevenly loaded
         GemmArgs g{};
         g.alpha = 1.0;
         g.M = wp.R;
@@ -965,26 +973,23 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
         g.K = wp.K;
         g.a = plain(wp.U, wp.R);           // A(m = r, k = i) = U[i][r]
         g.b = wp.y;
-        // K split in two when the 64 x 64 tiles alone leave the CUs unevenly loaded (FP64 partials,
-        // summed in order and rounded once)
         const int64_t cus = device_cu_count();
-        const int64_t tw = ((wp.R + 63) / 64) * ((wp.N + 63) / 64);
+        const int64_t tw = ((wp.R + 127) / 128) * ((wp.N + 63) / 64);
         auto balance = [&](int64_t t) { return ((double)t / cus) / (double)((t + cus - 1) / cus); };
-        const bool split_w =
-            wp.K >= 512 && 2 * wp.R * wp.N <= p.Wpart_elems && balance(2 * tw) > 1.05 * balance(tw);
+        const bool split_w = wp.K >= 512 && 2 * wp.R * wp.N <= part_cap && balance(2 * tw) > 1.05 * balance(tw);
         if (split_w) {
-            g.k_split = (((wp.K + 1) / 2) + 15) / 16 * 16;
-            g.c = plain(p.Wpart, wp.N);
+            g.k_split = (((wp.K + 1) / 2) + 31) / 32 * 32;
+            g.c = plain(part, wp.N);
             g.c_zstride = wp.R * wp.N;
-            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
-            TK_HIP(tk_sum_splits_to_f32(p.Wpart, (int)((wp.K + g.k_split - 1) / g.k_split), wp.R * wp.N, wp.R * wp.N,
-                                        W, r.st));
+            TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
+            TK_HIP(tk_sum_splits_f32p(part, (int)((wp.K + g.k_split - 1) / g.k_split), wp.R * wp.N, wp.R * wp.N, W,
+                                      r.st));
         } else {
             g.c = plain(W, wp.N);
-            g.c_f32 = 1;
-            TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, true, true, r.st));
+            TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
         }
-        // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W(k = (a, b), r), K split to fill the chip
+        // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W(k = (a, b), r) on the FP32 matrix cores, K split to
+        // fill the chip and to at most kZSplitK per split; FP32 partials summed in FP64 into Z
         GemmArgs h{};
         h.alpha = 1.0;
         h.M = s;
@@ -992,22 +997,18 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
         h.K = AB;
         h.a = folded(Y, B, B, s * B);      // A(m = i, k = (a, b))
         h.b = wz;                          // B(k = (a, b), n = r), same k segments as A
-        const int64_t tiles = ((s + 63) / 64) * ((R + 63) / 64);
-        int64_t splits = std::max<int64_t>(1, std::min<int64_t>(gram_capacity() / tiles, AB / 256));
-        splits = std::min<int64_t>(splits, std::max<int64_t>(1, p.Wpart_elems / (s * R)));
+        const int64_t tiles = ((s + 127) / 128) * ((R + 127) / 128);
+        int64_t splits = std::max<int64_t>(std::max<int64_t>(1, 2 * cus / tiles), (AB + kZSplitK - 1) / kZSplitK);
+        splits = std::min<int64_t>(splits, std::max<int64_t>(1, AB / 64));
+        splits = std::min<int64_t>(splits, std::max<int64_t>(1, part_cap / (s * R)));
         int64_t ks = (AB + splits - 1) / splits;
-        ks = (ks + 15) / 16 * 16;
+        ks = (ks + 31) / 32 * 32;
         const int nsplit = (int)((AB + ks - 1) / ks);
         h.k_split = ks;
-        if (nsplit > 1) {
-            h.c = plain(p.Wpart, R);
-            h.c_zstride = s * R;
-            TK_HIP(gemm_f64(h, MK, MK, EPI_STORE, true, true, r.st));
-            TK_HIP(tk_sum_splits_f64(p.Wpart, nsplit, s * R, s * R, p.Z, r.st));
-        } else {
-            h.c = plain(p.Z, R);
-            TK_HIP(gemm_f64(h, MK, MK, EPI_STORE, true, true, r.st));
-        }
+        h.c = plain(part, R);
+        h.c_zstride = s * R;
+        TK_HIP(gemm_f32(h, MK, MK, EPI_STORE, false, r.st));
+        TK_HIP(tk_sum_splits_f32p(part, nsplit, s * R, s * R, p.Z, r.st));
     }
     StageTimer t(r, stage_oi);
     orthonormalize(r, p.Z, false, s, R, p.U64[n], p.U32[n], false);
@@ -1816,8 +1817,8 @@ __global__ void fit_push_kernel(const double* __restrict__ src, int* counter, do
         *counter = k + 1;
     }
 }
-template <typename TO>
-__global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int64_t n, int64_t zstride,
+template <typename TO, typename TP = double>
+__global__ void sum_splits_kernel(const TP* __restrict__ P, int nsplit, int64_t n, int64_t zstride,
                                   TO* __restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -1830,7 +1831,7 @@ __global__ void sum_splits_kernel(const double* __restrict__ P, int nsplit, int6
             s += a2;
             s += a3;
         }
-        for (; z < nsplit; ++z) s += P[(int64_t)z * zstride + e];
+        for (; z < nsplit; ++z) s += (double)P[(int64_t)z * zstride + e];
         out[e] = (TO)s;
     }
 }
@@ -1890,6 +1891,16 @@ hipError_t tk_sum_splits_to_f32(const double* P, int nsplit, int64_t n, int64_t 
     hipLaunchKernelGGL(sum_splits_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
     return hipGetLastError();
 }
+// FP32 partials summed in FP64 in split order, stored as TO
+template <typename TO>
+hipError_t tk_sum_splits_f32p(const float* P, int nsplit, int64_t n, int64_t zstride, TO* out, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+    hipLaunchKernelGGL((sum_splits_kernel<TO, float>), dim3((unsigned)g), dim3(256), 0, s, P, nsplit, n, zstride, out);
+    return hipGetLastError();
+}
+template hipError_t tk_sum_splits_f32p<float>(const float*, int, int64_t, int64_t, float*, hipStream_t);
+template hipError_t tk_sum_splits_f32p<double>(const float*, int, int64_t, int64_t, double*, hipStream_t);
 hipError_t tk_resid_sumsq(const float* X, const float* Xh, int64_t n, double* partial, int nblocks, double* out,
                           hipStream_t s) {
     hipLaunchKernelGGL(resid_kernel, dim3(nblocks), dim3(256), 0, s, X, Xh, n, partial);
