@@ -94,6 +94,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // V2K: k-contiguous FP32 operands whose k runs are only 2-aligned (e.g. 42-long pixel fibres):
     // 8-byte vectors, two of each operand per thread (1024-element tiles)
     constexpr bool V2K = VEC == 2;
+    // V4K: k-contiguous (MK) FP32 operands with 4-aligned k runs on large tiles: 16-byte vectors,
+    // BM*BK/1024 of A and BN*BK/1024 of B per thread (vector tid + 256 u: row tid / (BK/4) + u 256 / (BK/4),
+    // k quad tid % (BK/4)); both operands share the k position (equal segment lengths)
+    constexpr bool V4K = VEC == 5;
+    static_assert(VEC != 5 || (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && (BM * BK) % 1024 == 0 &&
+                               (BN * BK) % 1024 == 0),
+                  "16-byte k-vectors need k-contiguous FP32 operands and whole vectors per thread");
+    constexpr int V4A = V4K ? BM * BK / 1024 : 1, V4B = V4K ? BN * BK / 1024 : 1;
     static_assert(VEC != 2 || (OA == MK && OB == MK && sizeof(TA) == 4 && sizeof(TB) == 4 && BM == BN &&
                                BM * BK == 1024),
                   "8-byte vector loads need k-contiguous FP32 operands and 1024-element tiles");
@@ -192,6 +200,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         v2c = KCol4{k / g.a.seg, k % g.a.seg};
     }
     float2 v2a[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    constexpr int v4_rstep = 256 / (BK / 4 > 0 ? BK / 4 : 1);
+    const int v4_row = tid / (BK / 4 > 0 ? BK / 4 : 1);
+    const int v4_k4 = tid % (BK / 4 > 0 ? BK / 4 : 1);
+    KCol4 v4c{0, 0};
+    if constexpr (V4K) {
+        const int64_t k = kbeg + 4 * v4_k4;
+        v4c = KCol4{k / g.a.seg, k % g.a.seg};
+    }
+    float4 v4a[V4A], v4b[V4B];
     float2 v2b[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
     auto ld2 = [&](const Desc& d, int64_t rows, int64_t row, int64_t k) {
         float2 v = make_float2(0.f, 0.f);
@@ -365,6 +382,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             }
             return;
         }
+        if constexpr (V4K) {
+            auto ld4 = [&](const Desc& d, int64_t rows, int64_t row, int64_t k) {
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (row < rows) {
+                    const TA* src = (const TA*)d.ptr + row * d.ld + v4c.kq * d.segstride + v4c.kr;
+                    if (k + 4 <= kend) {
+                        v = *(const float4*)src;
+                    } else {
+                        if (k < kend) v.x = src[0];
+                        if (k + 1 < kend) v.y = src[1];
+                        if (k + 2 < kend) v.z = src[2];
+                    }
+                }
+                return v;
+            };
+            const int64_t k = k0 + 4 * v4_k4;
+#pragma unroll
+            for (int u = 0; u < V4A; ++u) v4a[u] = ld4(g.a, g.M, m0 + v4_row + v4_rstep * u, k);
+#pragma unroll
+            for (int u = 0; u < V4B; ++u) v4b[u] = ld4(g.b, g.N, n0 + v4_row + v4_rstep * u, k);
+            v4c.kr += BK;
+            while (v4c.kr >= g.a.seg) {
+                v4c.kr -= g.a.seg;
+                ++v4c.kq;
+            }
+            return;
+        }
         if constexpr (V2K) {
             const int64_t k = k0 + 2 * v2_kw;
 #pragma unroll
@@ -449,6 +493,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 d2[2] = (T)vk_reg2.z;
                 d2[3] = (T)vk_reg2.w;
             }
+            return;
+        }
+        if constexpr (V4K) {
+#pragma unroll
+            for (int u = 0; u < V4A; ++u) *(float4*)&As[(v4_row + v4_rstep * u) * LDA + 4 * v4_k4] = v4a[u];
+#pragma unroll
+            for (int u = 0; u < V4B; ++u) *(float4*)&Bs[(v4_row + v4_rstep * u) * LDB + 4 * v4_k4] = v4b[u];
             return;
         }
         if constexpr (V2K) {
@@ -691,6 +742,16 @@ hipError_t launch_one(const GemmArgs& g, hipStream_t s) {
         // one k position for both operands: equal segment lengths (each keeps its own stride)
         if (ok2(g.a) && ok2(g.b) && g.a.seg == g.b.seg && g.k_split % 2 == 0) {
             hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 2>), grid, dim3(256), 0, s,
+                               g);
+            return hipGetLastError();
+        }
+    }
+    constexpr bool can_v4k = OA == MK && OB == MK && sizeof(T) == 4 && sizeof(TA) == 4 && sizeof(TB) == 4 && !ACC64 &&
+                             (BM * BK) % 1024 == 0 && (BN * BK) % 1024 == 0 && BM * BK > 1024;
+    if constexpr (can_v4k) {
+        // 16-byte k-vectors on large FP32 tiles: both operands 4-aligned k runs of equal segment length
+        if (km_vec_ok(g.a) && km_vec_ok(g.b) && g.a.seg == g.b.seg && g.k_split % 4 == 0) {
+            hipLaunchKernelGGL((gemm_kernel<T, TA, TB, OA, OB, EPI, ACC64, BM, BN, BK, 5>), grid, dim3(256), 0, s,
                                g);
             return hipGetLastError();
         }
