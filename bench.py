@@ -51,10 +51,9 @@ def stage_work(dims, ranks, precision="fp32"):
     Returns {stage: (kind, amount)} with kind 'hbm' (bytes) or a matrix-core type 'f32', 'f64',
     'bf16', 'f16', 'fp8' (flops).  Bytes are the reads of the input and writes of the output
     once; flops are 2 * MACs (the Gram counts the lower triangle it computes: s^2 K).  In FP32
-    the mode updates run on the FP64 matrix cores (FP32 data, exact products, FP64 accumulation):
-    with one orthogonal-iteration step per sweep (the default) the gram stages time the two
-    products W = Y x_n U^T and Y_(n) W_(n)^T (mode 2 forms W from the mode-1 tensor, contracting
-    over s1); the mode products run on the FP32 matrix cores.  In reduced precision every contraction runs in the 16-bit
+    every product runs on the FP32 matrix cores: with one orthogonal-iteration step per sweep (the
+    default) the gram stages time the two products W = Y x_n U^T and Y_(n) W_(n)^T (mode 2 forms W
+    from the mode-1 tensor, contracting over s1) with their split sums.  In reduced precision every contraction runs in the 16-bit
     type (FP8: the two products over X in FP8, the rest in BF16) and the two full-tensor passes
     are priced by their bytes (X in the storage type, outputs in the 16-bit type, T34 rows padded
     to a multiple of 8).
@@ -66,11 +65,11 @@ def stage_work(dims, ranks, precision="fp32"):
         return {
             "pass_a": ("hbm", 4 * (s0 * s1 * L + s0 * s1 * r23)),
             "ttm_y1": ("f32", 2 * r1 * s1 * (s0 * r23)),
-            "gram_1": ("f64", 4 * s0 * r0 * (r1 * r23)),
+            "gram_1": ("f32", 4 * s0 * r0 * (r1 * r23)),
             # Y2 = T1 x_3 U3^T x_4 U4^T: the fibre kernel on T1 (pass C1 runs before mode 2)
             "ttm_y2": ("hbm", 4 * (r0 * s1 * L + r0 * s1 * r23)),
             # mode 2: W = Y1 x_1 U1^T from the mode-1 tensor (contracted over s1), then Y2_(2) W_(2)^T
-            "gram_2": ("f64", 2 * r0 * s0 * (r1 * r23) + 2 * s1 * r1 * (r0 * r23)),
+            "gram_2": ("f32", 2 * r0 * s0 * (r1 * r23) + 2 * s1 * r1 * (r0 * r23)),
             "pass_c1": ("f32", 2 * r0 * s0 * (s1 * L)),
             "ttm_c2": ("f32", 2 * r1 * s1 * (r0 * L)),
         }
