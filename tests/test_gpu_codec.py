@@ -60,6 +60,29 @@ def test_sym_eig_blocked_matches_lapack(ctx, n, r):
         assert np.linalg.norm(u - vt @ (vt.T @ u), 2) <= 1e-6 + 1e-12 / gap
 
 
+@pytest.mark.parametrize("n", [96, 448])
+def test_sym_eig_blocked_repeated_and_graded_eigenvalues(ctx, n):
+    """Exactly repeated eigenvalues (clusters of 8), a zero block and a graded tail: the
+    eigenvalues to the backward-stable bound, the eigenvectors orthonormal, and the residual
+    ||S U - U diag(lam)|| small against ||S||.  Within a cluster any orthonormal basis is correct, so
+    the subspaces, not the vectors, are compared through the residual."""
+    rng = np.random.default_rng(7 + n)
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat(np.geomspace(1.0, 1e-5, n // 8), 8)[:n]
+    lam[-8:] = 0.0
+    s = ((q * lam) @ q.T).astype(np.float32)
+    s = (s + s.T) / 2
+    _say(f"sym_eig repeated n={n}")
+    u, lg = ctx.sym_eig(_dev(s), n)
+    u = u.cpu().numpy().astype(np.float64)
+    lg = lg.cpu().numpy()
+    s64 = s.astype(np.float64)
+    ref = np.linalg.eigvalsh(s64)[::-1]
+    assert np.max(np.abs(lg - ref)) <= 50 * n * 2.0 ** -53 * ref[0]
+    assert np.linalg.norm(u.T @ u - np.eye(n), 2) <= 1e-5                  # FP32 vectors
+    assert np.linalg.norm(s64 @ u - u * lg, 2) <= 1e-5 * ref[0]
+
+
 def _slice_offdiag(g, n):
     gn = np.moveaxis(g, n, 0).reshape(g.shape[n], -1)
     c = gn @ gn.T

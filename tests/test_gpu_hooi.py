@@ -157,25 +157,30 @@ def test_stack_matches_oracle(ctx, name, sweeps):
     _stack_checks(x32, ranks, g, o, INIT_ITERS + iters, name)
 
 
+@pytest.mark.parametrize("start", ["thosvd", "sthosvd"])
 @pytest.mark.parametrize("name", ["stack_mini", "stack_mini_ipt"])
-def test_oversampled_start_is_the_thosvd(name):
+def test_oversampled_start_is_the_thosvd(name, start):
     """With oversampling the cold start iterates on R + p columns and closes with a Rayleigh-Ritz
     step, so its leading directions converge at lam_{R+p+1} / lam_i: the start (max_iters = 0) is the
-    oracle's T-HOSVD (Sec. III-B.1, eq. (6)-(7)) within the Rayleigh-Ritz bound of tests/allowances.py,
-    close rank boundaries included.  The plain start misses the boundary directions by far more than
-    that bound (sin theta 0.4 .. 0.9 on these stacks)."""
+    oracle's T-HOSVD (Sec. III-B.1, eq. (6)-(7)), or its sequentially truncated variant, within the
+    Rayleigh-Ritz bound of tests/allowances.py, close rank boundaries included.  The plain start misses
+    the boundary directions by far more than that bound (sin theta 0.4 .. 0.9 on these stacks).  The
+    later modes of the sequentially truncated start are eigenvectors of the Gram of the FP32 projection
+    of X on the earlier factors, whose rounding may turn a direction at a nearly degenerate boundary
+    (gap factor lam_1 / (lam_R - lam_{R+1}) = 1.6e8 for stack_mini's second mode) by more than the
+    iteration bound: there only the reconstruction binds."""
     import paper_2104_04726_amd as tk
     from allowances import rr_allowance, rr_sine_bound
     c = STACK_CONFIGS[name]
     x32 = make_stereo_stack(c["H"], c["W"], c["E"], c["colorspace"], c["seed"])
     ranks, p = c["ranks"], 32
-    ctx2 = tk.Context(0, oversample=p)
+    ctx2 = tk.Context(0, oversample=p, start=start)
     try:
-        _say(f"stack {name}, start only, oversample {p}")
+        _say(f"stack {name}, {start} start only, oversample {p}")
         g = _gpu(ctx2, x32, ranks, 0)
     finally:
         ctx2.close()
-    o = _ora(x32, ranks, 0)
+    o = _ora(x32, ranks, 0, start=start)
     m = oracle.compare(g, o)
     res = o["res"]
     recon_tol = 1e-5 + rr_allowance(res.spectra, x32.shape, ranks, INIT_ITERS, p)
@@ -188,8 +193,9 @@ def test_oversampled_start_is_the_thosvd(name):
     for n, (sz, r) in enumerate(zip(x32.shape, ranks)):
         if r < sz and sz > 64:
             large += 1
-            bound = 1e-5 + rr_sine_bound(res.spectra[n], sz, r, INIT_ITERS, p)
-            assert m["sin_theta"][n] <= bound, (n, m["sin_theta"][n], bound)
+            if start == "thosvd" or n == 0:
+                bound = 1e-5 + rr_sine_bound(res.spectra[n], sz, r, INIT_ITERS, p)
+                assert m["sin_theta"][n] <= bound, (n, m["sin_theta"][n], bound)
     st = g["stats"]
     assert st["oi_steps_init"] == large * INIT_ITERS
     assert st["rr_sweeps"] >= large            # every Rayleigh-Ritz step ran at least one sweep
