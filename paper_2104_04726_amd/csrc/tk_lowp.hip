@@ -112,11 +112,14 @@ __global__ __launch_bounds__(256) void from_lp_kernel(const typename Codec<P>::S
 
 // ---------------------------------------------------------------------------- two-mode pass
 // Fixed-shape version of the pass below (P x Q fibres, ranks R3, R4, output rows of LDO): the
-// chunk of 256 fibres is read with 16-byte coalesced loads prefetched one chunk ahead, decoded
-// into LDS, mapped one fibre per thread with U3 in registers and U4 in LDS, and written back with
-// 16-byte stores.  ID3: U3 is the identity (a mode kept at full rank), so its product is skipped.  Only FP8
-// carries slice scales.  The decode walks each 16-byte vector's elements with one division per
-// vector (fibre and position advance by increments).
+// chunk of 256 fibres is read with 16-byte coalesced loads prefetched one chunk ahead, mapped one
+// fibre per thread with U3 in registers and U4 in LDS, and written back with 16-byte stores.
+// ID3: U3 is the identity (a mode kept at full rank), so its product is skipped.  16-bit storage:
+// each thread decodes the elements of its 16-byte vectors into an FP32 copy of the chunk in LDS
+// (one division per vector; fibre and position advance by increments).  FP8 (16 elements per
+// vector, slice scales): that decode wrote LDS with 16-way bank conflicts, so the chunk is stored
+// to LDS as it is (16-byte stores, consecutive lanes on consecutive addresses) and each thread
+// decodes and scales its own fibre from there, two elements per 2-byte read and conversion.
 template <int P, int OUTP, int PP, int QQ, int R3, int R4, int LDO, bool ID3>
 __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S* __restrict__ in, int64_t A,
                                                      const float* __restrict__ U3, const float* __restrict__ U4,
@@ -130,10 +133,15 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
     constexpr int VPT = (NV_IN + 255) / 256;
     constexpr int NV_OUT = FPB * LDO * 2 / 16;
     constexpr bool SCALED = (P == LP_FP8);
+    constexpr bool RAW = (ES == 1);                     // stage the chunk as stored, decode per fibre
     static_assert((FPB * LIN) % EPV == 0 && (FPB * LDO * 2) % 16 == 0, "chunk not a whole number of vectors");
     static_assert(!ID3 || PP == R3, "an identity U3 keeps the mode's size");
-    static_assert(EPV <= LIN, "a vector spans at most two fibres");
-    __shared__ float fin[FPB * SIN];
+    static_assert(EPV <= LIN || RAW, "a vector spans at most two fibres");
+    static_assert(!RAW || LIN % 2 == 0, "FP8 fibres are read two elements at a time");
+    constexpr int NFIN = RAW ? 1 : FPB * SIN;
+    constexpr int NRAW = RAW ? FPB * LIN : 16;
+    __shared__ float fin[NFIN];
+    __shared__ __attribute__((aligned(16))) S raw[NRAW];
     __shared__ __attribute__((aligned(16))) uint16_t fout[FPB * LDO];
     __shared__ float sc[LIN];
     __shared__ float u4[QQ * R4];
@@ -163,7 +171,18 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
         const int64_t f0 = ch * FPB;
         const int nf = (int)((A - f0) < FPB ? (A - f0) : FPB);
         __syncthreads();
-        if (ch < full) {
+        if constexpr (RAW) {
+            if (ch < full) {
+#pragma unroll
+                for (int u = 0; u < VPT; ++u) {
+                    const int i = threadIdx.x + 256 * u;
+                    if (i < NV_IN) ((uint4*)raw)[i] = pre[u];
+                }
+            } else {
+                const S* src = in + f0 * LIN;
+                for (int g = threadIdx.x; g < nf * LIN; g += 256) raw[g] = src[g];
+            }
+        } else if (ch < full) {
 #pragma unroll
             for (int u = 0; u < VPT; ++u) {
                 const int i = threadIdx.x + 256 * u;
@@ -175,8 +194,7 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
                     float* dst = fin + fb * SIN;
 #pragma unroll
                     for (int j = 0; j < EPV; ++j) {
-                        const float v = Codec<P>::dec(e[j]);
-                        dst[l] = SCALED ? v * sc[l] : v;
+                        dst[l] = Codec<P>::dec(e[j]);
                         ++l;
                         if (l == LIN) {
                             l = 0;
@@ -187,17 +205,25 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
             }
         } else {
             const S* src = in + f0 * LIN;
-            for (int g = threadIdx.x; g < nf * LIN; g += 256) {
-                const int l = g % LIN;
-                const float v = Codec<P>::dec(src[g]);
-                fin[(g / LIN) * SIN + l] = SCALED ? v * sc[l] : v;
-            }
+            for (int g = threadIdx.x; g < nf * LIN; g += 256) fin[(g / LIN) * SIN + g % LIN] = Codec<P>::dec(src[g]);
         }
         __syncthreads();
         prefetch(ch + gridDim.x);
         const int f = threadIdx.x;
         if (f < nf) {
+            float xv[RAW ? LIN : 1];
+            if constexpr (RAW) {
+                const uint16_t* xp = (const uint16_t*)(raw + f * LIN);
+#pragma unroll
+                for (int h = 0; h < LIN / 2; ++h) {
+                    // the hardware conversion of both bytes of the 16-bit word (element 2h in the low byte)
+                    const auto v2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)xp[h], false);
+                    xv[2 * h] = v2[0] * sc[2 * h];
+                    xv[2 * h + 1] = v2[1] * sc[2 * h + 1];
+                }
+            }
             const float* x = fin + f * SIN;
+            auto elem = [&](int l) { return RAW ? xv[RAW ? l : 0] : x[l]; };
             float tmp[PP][R4];
 #pragma unroll
             for (int c = 0; c < PP; ++c)
@@ -207,7 +233,7 @@ __global__ __launch_bounds__(256) void pair_lp_fixed(const typename Codec<P>::S*
             for (int i = 0; i < QQ; ++i) {
                 float xc[PP];
 #pragma unroll
-                for (int c = 0; c < PP; ++c) xc[c] = x[c * QQ + i];
+                for (int c = 0; c < PP; ++c) xc[c] = elem(c * QQ + i);
 #pragma unroll
                 for (int t = 0; t < R4; ++t) {
                     const float w = u4[i * R4 + t];
