@@ -134,10 +134,10 @@ typedef struct {
                                     its R_n largest Ritz values.  The leading directions then
                                     converge at the rate lam_{Rc+1} / lam_i instead of
                                     lam_{R+1} / lam_i, which resolves close rank boundaries.  Rc
-                                    must not exceed 1024 (else TUCKER_ERR_UNSUPPORTED).  The two
-                                    large modes' starts then run one after the other on the
-                                    context's stream (the eigensolver checks its convergence on
-                                    the host).  0 (default): no oversampling, no Rayleigh-Ritz. */
+                                    must not exceed 1024 (else TUCKER_ERR_UNSUPPORTED).  The
+                                    eigensolver checks its convergence on the host after each
+                                    sweep; the two large modes' eigensolvers run side by side on
+                                    two streams.  0 (default): no oversampling, no Rayleigh-Ritz. */
 } tucker_options;
 
 /* Stages timed when tucker_options.timing is set (names follow a sweep of an order-4 stack

@@ -72,6 +72,8 @@ struct tucker_ctx {
     bool async_alloc = false;       // workspace from the stream-ordered allocator (server slots)
     hipStream_t aux = nullptr;      // second stream: the cold start of mode 1 beside that of mode 2
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    double* eig_host = nullptr;     // pinned convergence sums of two interleaved eigensolver runs
+    hipEvent_t eig_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -414,6 +416,7 @@ void build_plan(Plan& p, Arena& a) {
         p.Q1b = a.take<double>(s0 * R0);
         p.Wb = a.take<double>(R0 * R0);
         p.Wpartb_elems = std::max<int64_t>(16 * R0 * R0, 8 * s0 * R0);
+        if (R0 > 0 && R0 <= 1024) p.Wpartb_elems = std::max(p.Wpartb_elems, sym_eig_work_doubles((int)R0));
         p.Wpartb = a.take<double>(p.Wpartb_elems);
         p.Tmb = a.take<double>(R0 * R0);
         p.chol_wsb = a.take<int>(chol_counter_ints(R0));
@@ -457,6 +460,7 @@ struct Run {
     int oi_steps_init = 0, oi_steps_sweeps = 0;   // orthogonal-iteration steps taken (host count)
     double oi_resid_max = 0.0;  // inner_tol > 0: largest final relative residual of an update
     int rr_sweeps = 0;          // block-Jacobi sweeps of the Rayleigh-Ritz steps (oversampled starts)
+    bool defer_ritz = false;    // an oversampled cold start leaves its Rayleigh-Ritz step to the caller
 
     long long spin() const { return (long long)ctx->opt.wait_spin_limit; }
     double inner_tol() const { return ctx->opt.inner_tol; }
@@ -834,11 +838,12 @@ void su_product(Run& r, int n, int64_t cols) {
 // Rayleigh-Ritz step closing an oversampled cold start (Rc = p.Rc[n] > R columns): with U (s x Rc,
 // orthonormal) in U64[n], B = U^T S U (Rc x Rc) is diagonalised in FP64 (block Jacobi) and the
 // factor becomes U V_R (s x R), V_R the eigenvectors of the R largest Ritz values, descending.  U V_R
-// is orthonormal to FP64 rounding (both factors are).  The eigensolver synchronises the stream once
-// per Jacobi sweep.
-void rayleigh_ritz(Run& r, int n) {
+// is orthonormal to FP64 rounding (both factors are).  In three parts: the products up to B (into
+// p.W), the eigensolver (V_R into p.Tm, scratch in p.Wpart), and U V_R; the eigensolver checks its
+// convergence on the host after each sweep.
+void ritz_products(Run& r, int n) {
     Plan& p = r.p;
-    const int64_t s = p.s[n], R = p.R[n], Rc = p.Rc[n];
+    const int64_t s = p.s[n], Rc = p.Rc[n];
     if (sym_eig_work_doubles((int)Rc) > p.Wpart_elems)
         throw Fail{TUCKER_ERR_OUT_OF_MEMORY, "Rayleigh-Ritz scratch too small"};
     su_product(r, n, Rc);
@@ -852,9 +857,10 @@ void rayleigh_ritz(Run& r, int n) {
     g.c = plain(p.W, Rc);
     g.k_split = s;
     TK_HIP(gemm_f64(g, KM, KM, EPI_STORE, false, false, r.st));
-    int sweeps = 0;
-    TK_HIP(sym_eig_blocked(p.W, (int)Rc, (int)R, nullptr, p.Tm, nullptr, p.Wpart, r.st, &sweeps));
-    r.rr_sweeps += sweeps;
+}
+void ritz_rotate(Run& r, int n) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n], R = p.R[n], Rc = p.Rc[n];
     GemmArgs h{};
     h.alpha = 1.0;
     h.M = s;
@@ -867,6 +873,61 @@ void rayleigh_ritz(Run& r, int n) {
     TK_HIP(gemm_f64(h, MK, KM, EPI_STORE, false, false, r.st));
     TK_HIP(hipMemcpyAsync(p.U64[n], p.Q1, s * R * sizeof(double), hipMemcpyDeviceToDevice, r.st));
     TK_HIP(f64_to_f32(p.U64[n], p.U32[n], s * R, r.st));
+}
+void rayleigh_ritz(Run& r, int n) {
+    Plan& p = r.p;
+    ritz_products(r, n);
+    int sweeps = 0;
+    TK_HIP(sym_eig_blocked(p.W, (int)p.Rc[n], (int)p.R[n], nullptr, p.Tm, nullptr, p.Wpart, r.st, &sweeps));
+    r.rr_sweeps += sweeps;
+    ritz_rotate(r, n);
+}
+
+// The Rayleigh-Ritz steps of the two large modes of a concurrent start: mode 0 on the main stream with
+// the active scratch set, mode 1 on the second stream with the other set; the sweeps of their
+// eigensolvers are interleaved (each waits only for its own convergence test), so the two run side by
+// side.
+void rayleigh_ritz_pair(Run& r) {
+    Plan& p = r.p;
+    tucker_ctx* ctx = r.ctx;
+    if (!ctx->eig_host) {
+        void* h = nullptr;
+        TK_HIP(hipHostMalloc(&h, 4 * sizeof(double), hipHostMallocDefault));
+        ctx->eig_host = (double*)h;
+    }
+    for (auto& e : ctx->eig_ev)
+        if (!e) TK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    SymEigRun e[2];
+    auto setup = [&](int n, int k) {
+        ritz_products(r, n);
+        e[k].A = p.W;
+        e[k].n = (int)p.Rc[n];
+        e[k].r = (int)p.R[n];
+        e[k].U = p.Tm;
+        e[k].work = p.Wpart;
+        e[k].s = r.st;
+        e[k].host = ctx->eig_host + 2 * k;
+        e[k].ev = ctx->eig_ev[k];
+        TK_HIP(sym_eig_start(e[k]));
+    };
+    setup(0, 0);
+    swap_oi(p);
+    {
+        OnAux aux(r);
+        setup(1, 1);
+    }
+    swap_oi(p);
+    while (!e[0].done || !e[1].done)
+        for (auto& j : e)
+            if (!j.done) TK_HIP(sym_eig_step(j));
+    r.rr_sweeps += e[0].sweeps + e[1].sweeps;
+    ritz_rotate(r, 0);
+    swap_oi(p);
+    {
+        OnAux aux(r);
+        ritz_rotate(r, 1);
+    }
+    swap_oi(p);
 }
 
 // q steps of orthogonal iteration on S64 (s x s), from U64: Z = S U in FP64, then CholeskyQR.  With
@@ -904,7 +965,7 @@ void orth_iter(Run& r, int n, int q, bool cold) {
         (cold ? r.oi_steps_init : r.oi_steps_sweeps) += 1;
     }
     if (tol > 0.0) r.oi_resid_max = std::max(r.oi_resid_max, resid);
-    if (ritz) rayleigh_ritz(r, n);
+    if (ritz && !r.defer_ritz) rayleigh_ritz(r, n);
 }
 
 // factor update of mode n from the Gram in S64
@@ -1113,10 +1174,39 @@ void thosvd(Run& r) {
     lp_start_copy(r);
     bool ritz = false;
     for (int n = 0; n < p.N; ++n) ritz = ritz || p.Rc[n] > p.R[n];
-    if (!p.has_alt || r.inner_tol() > 0.0 || ritz) {
-        // (with a tolerance, or the Rayleigh-Ritz eigensolver, the host waits for the device inside
-        // a mode's start, so the two streams could not overlap)
+    if (!p.has_alt || r.inner_tol() > 0.0) {
+        // (with a tolerance every step waits for the host, so the two streams could not overlap)
         modes_from(0);
+        return;
+    }
+    if (ritz) {
+        // oversampled: the two cold iterations run side by side as below, then their Rayleigh-Ritz
+        // steps (whose eigensolvers wait for the host) side by side, then the small modes
+        start_gram(r, 1);
+        fork_aux(r);
+        r.defer_ritz = p.Rc[1] > p.R[1];
+        {
+            OnAux aux(r);
+            update_factor(r, 1, true);
+        }
+        const bool deferred1 = r.defer_ritz;
+        swap_oi(p);
+        start_gram(r, 0);
+        r.defer_ritz = p.Rc[0] > p.R[0] && deferred1;
+        update_factor(r, 0, true);
+        r.defer_ritz = false;
+        if (deferred1 && p.Rc[0] > p.R[0]) rayleigh_ritz_pair(r);
+        else if (deferred1) {
+            swap_oi(p);
+            {
+                OnAux aux(r);
+                rayleigh_ritz(r, 1);
+            }
+            swap_oi(p);
+        }
+        modes_from(2);
+        swap_oi(p);
+        join_aux(r);
         return;
     }
     // the modes start from the unprojected X independently.  Mode 2's Gram (the larger) comes first,
@@ -2087,6 +2177,9 @@ tucker_status tucker_destroy(tucker_ctx* ctx) {
         (void)hipStreamDestroy(ctx->aux);
     }
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    for (auto& e : ctx->eig_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->eig_host) (void)hipHostFree(ctx->eig_host);
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

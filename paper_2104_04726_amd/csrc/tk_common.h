@@ -164,6 +164,26 @@ int64_t chol_counter_ints(int64_t n);
 int64_t sym_eig_work_doubles(int n);
 hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U, float* U32, double* work,
                            hipStream_t s, int* sweeps_out = nullptr);
+// The same eigensolver in steps, so that several can run on different streams side by side:
+// sym_eig_start enqueues the set-up and the first convergence test (its two sums copied to the
+// pinned host pair `host`, completion marked by `ev`); each sym_eig_step waits for the pending test,
+// then enqueues either one sweep and the next test or (converged, or 40 sweeps) the final sort and
+// gather, and sets done.  The caller owns host (pinned, 2 doubles) and ev.
+struct SymEigRun {
+    const double* A = nullptr;
+    int n = 0, r = 0;
+    double* lam = nullptr;
+    double* U = nullptr;
+    float* U32 = nullptr;
+    double* work = nullptr;
+    hipStream_t s = nullptr;
+    double* host = nullptr;
+    hipEvent_t ev = nullptr;
+    int sweeps = 0;
+    bool done = false;
+};
+hipError_t sym_eig_start(SymEigRun& j);
+hipError_t sym_eig_step(SymEigRun& j);
 
 // ---------------------------------------------------------------------------------------
 // Autotuner (tk_tune.hip): measured launch choices cached per (operation, shape, device)

@@ -374,4 +374,74 @@ hipError_t sym_eig_blocked(const double* A, int n, int r, double* lam, double* U
     return hipGetLastError();
 }
 
+// ---- the same eigensolver in steps (SymEigRun, tk_common.h)
+namespace {
+struct EigLayout {
+    int np, T, nbo;
+    unsigned g2, napply;
+    double *Ap, *V, *Qbuf, *partial, *scal;
+    int* rank;
+};
+EigLayout eig_layout(int n, double* work) {
+    EigLayout L;
+    L.np = ((n + 63) / 64) * 64;
+    L.T = L.np / EB;
+    L.Ap = work;
+    L.V = L.Ap + (int64_t)L.np * L.np;
+    L.Qbuf = L.V + (int64_t)L.np * L.np;
+    L.partial = L.Qbuf + (int64_t)(L.T / 2) * SP * SP;
+    L.scal = L.partial + 2 * 1024;
+    L.rank = reinterpret_cast<int*>(L.scal + 16);
+    L.g2 = grid_for_elems((int64_t)L.np * L.np);
+    L.nbo = (int)std::min<unsigned>(L.g2, 64);
+    L.napply = (unsigned)((L.T / 2) * (L.T / 2 + 1) / 2 + (L.np / SP) * (L.T / 2));
+    return L;
+}
+// the convergence test of the current matrix: off-diagonal and total mass to the pinned host pair
+hipError_t eig_check(const SymEigRun& j, const EigLayout& L) {
+    hipLaunchKernelGGL(offnorm_kernel, dim3(L.nbo), dim3(256), 0, j.s, L.Ap, L.np, L.partial);
+    hipLaunchKernelGGL(offnorm_fold_kernel, dim3(1), dim3(256), 0, j.s, L.partial, L.nbo, L.scal);
+    hipError_t e = hipMemcpyAsync(j.host, L.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, j.s);
+    if (e == hipSuccess) e = hipEventRecord(j.ev, j.s);
+    return e;
+}
+}  // namespace
+
+hipError_t sym_eig_start(SymEigRun& j) {
+    if (j.n < 1 || j.n > 1024 || j.r < 1 || j.r > j.n || !j.host || !j.ev) return hipErrorInvalidValue;
+    const EigLayout L = eig_layout(j.n, j.work);
+    j.sweeps = 0;
+    j.done = false;
+    hipLaunchKernelGGL(offnorm_kernel, dim3(L.nbo), dim3(256), 0, j.s, j.A, j.n, L.partial);
+    hipLaunchKernelGGL(offnorm_fold_kernel, dim3(1), dim3(256), 0, j.s, L.partial, L.nbo, L.scal + 2);
+    hipLaunchKernelGGL(eig_init_kernel, dim3(L.g2), dim3(256), 0, j.s, j.A, j.n, L.np, L.scal + 2, L.Ap, L.V);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return eig_check(j, L);
+}
+
+hipError_t sym_eig_step(SymEigRun& j) {
+    if (j.done) return hipSuccess;
+    const EigLayout L = eig_layout(j.n, j.work);
+    hipError_t e = hipEventSynchronize(j.ev);
+    if (e != hipSuccess) return e;
+    const bool converged = !(j.host[0] > (double)L.np * 0x1p-100 * j.host[1]);
+    if (converged || j.sweeps >= 40) {
+        hipLaunchKernelGGL(eig_sort_kernel, dim3((L.np + 255) / 256), dim3(256), 0, j.s, L.Ap, j.n, L.np, L.rank,
+                           j.lam);
+        hipLaunchKernelGGL(eig_gather_kernel, dim3(grid_for_elems((int64_t)j.n * L.np)), dim3(256), 0, j.s, L.V,
+                           L.rank, j.n, L.np, j.r, j.U, j.U32);
+        j.done = true;
+        return hipGetLastError();
+    }
+    for (int rr = 0; rr < L.T - 1; ++rr) {
+        hipLaunchKernelGGL(bj_solve_kernel, dim3(L.T / 2), dim3(256), 0, j.s, L.Ap, L.np, L.T, rr, L.Qbuf);
+        hipLaunchKernelGGL(bj_apply_kernel, dim3(L.napply), dim3(256), 0, j.s, L.Ap, L.V, L.np, L.T, rr, L.Qbuf);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ++j.sweeps;
+    return eig_check(j, L);
+}
+
 }  // namespace tk
