@@ -958,9 +958,10 @@ void orth_iter(Run& r, int n, int q, bool cold) {
         }
         // cold start: shifted CholeskyQR3 for the first two steps, one pass for the intermediate
         // ones, the checked CholeskyQR2 for the last; with a tolerance every step may be the last,
-        // so every step after the first two is a checked CholeskyQR2.  The FP32 copy is written
-        // only for a basis of the factor's own width.
-        const bool mid = cold && it >= 2 && it < q - 1 && tol <= 0.0;
+        // so every step after the first two is a checked CholeskyQR2.  A warm update of several
+        // steps likewise takes one pass for all but its last step (its warm basis keeps Z well
+        // conditioned).  The FP32 copy is written only for a basis of the factor's own width.
+        const bool mid = tol <= 0.0 && it < q - 1 && (cold ? it >= 2 : true);
         orthonormalize(r, p.Z, false, s, R, p.U64[n], ritz ? nullptr : p.U32[n], cold && it < 2, mid);
         (cold ? r.oi_steps_init : r.oi_steps_sweeps) += 1;
     }
