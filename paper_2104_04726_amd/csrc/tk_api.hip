@@ -713,10 +713,13 @@ void apply_tri(Run& r, const void* A, bool a32, int64_t rows, int64_t cols, cons
 // second pass runs only when the first left max_ij |(Q1^T Q1 - I)_ij| above kOrthTol: the test and
 // the skip happen on the device (the second pass's kernels return at once), so nothing waits on
 // the host.  Column scaling makes the first pass nearly exact when the columns of Z are close to
-// orthogonal, which is the case once the leading columns have settled.  Each pass maps the basis
-// by an invertible triangular factor, so the column space is that of Z.
+// orthogonal, which is the case once the leading columns have settled.  mid (an intermediate step
+// of a multi-step iteration): one plain pass into U64 only, which carries span(Z) into the next
+// product.  Each pass maps the basis by an invertible triangular factor, so the column space is that
+// of Z.  U32 (nullable) receives the FP32 copy of the final basis.
 constexpr double kOrthTol = 1e-12;     // FP32 sweeps: the factors are orthonormal to FP64 rounding
-constexpr double kOrthTolLowp = 1e-6;  // reduced-precision sweeps: far below their 2^-8..2^-4 operands
+constexpr double kOrthTolLowp = 1e-6;  // reduced-precision sweeps: far below the 2^-8..2^-4 rounding of
+                                       // the factor copies their products use
 
 void orthonormalize(Run& r, const void* Z, bool z32, int64_t rows, int64_t cols, double* U64, float* U32,
                     bool cold, bool mid = false) {
