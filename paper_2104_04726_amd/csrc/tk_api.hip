@@ -134,6 +134,7 @@ struct Plan {
     float *xscale = nullptr, *u1scale = nullptr, *spart = nullptr;
     float* Pf = nullptr;     // FP32 Gram partials
     int64_t Pf_elems = 0;
+    float* S32 = nullptr;    // FP32 copy of the sweep Grams (reduced-precision sweeps)
 
     float* U32[TUCKER_MAX_ORDER]{};
     bool ident[TUCKER_MAX_ORDER]{};     // U_n is exactly the identity (a full-rank mode started from it)
@@ -334,6 +335,7 @@ void build_plan(Plan& p, Arena& a) {
             if (p.lp_start)
                 p.Pf_elems = std::max(p.Pf_elems, std::max(lp_gram_partials(s0, s1 * p.Lp), lp_gram_partials(s1, s0 * p.Lp)));
             p.Pf = a.take<float>(p.Pf_elems);
+            p.S32 = a.take<float>(std::max(s0 * s0, s1 * s1));
         }
     } else {
         const int64_t cm = chain_max(p);
@@ -461,6 +463,7 @@ struct Run {
     double oi_resid_max = 0.0;  // inner_tol > 0: largest final relative residual of an update
     int rr_sweeps = 0;          // block-Jacobi sweeps of the Rayleigh-Ritz steps (oversampled starts)
     bool defer_ritz = false;    // an oversampled cold start leaves its Rayleigh-Ritz step to the caller
+    bool lp_su = false;         // reduced-precision sweep: warm S U from the FP32 copy of S
 
     long long spin() const { return (long long)ctx->opt.wait_spin_limit; }
     double inner_tol() const { return ctx->opt.inner_tol; }
@@ -838,6 +841,34 @@ void su_product(Run& r, int n, int64_t cols) {
     }
 }
 
+// Z = S U from the FP32 copies of S (p.S32) and U (U32[n]) in a reduced-precision sweep, whose Gram
+// already carries the 2^-8 .. 2^-4 rounding of its operands: FP32 MFMA, K split only as far as
+// filling the chip needs, FP32 partials summed in FP64 into p.Z.
+void su_product_f32(Run& r, int n, int64_t R) {
+    Plan& p = r.p;
+    const int64_t s = p.s[n];
+    float* part = reinterpret_cast<float*>(p.Wpart);
+    const int64_t part_cap = 2 * p.Wpart_elems;
+    GemmArgs g{};
+    g.alpha = 1.0;
+    g.M = s;
+    g.N = R;
+    g.K = s;
+    g.a = plain(p.S32, s);      // A(m, k) = S[k][m] (symmetric)
+    g.b = plain(p.U32[n], R);
+    const int64_t tiles = ((s + 127) / 128) * ((R + 127) / 128);
+    int64_t splits = std::max<int64_t>(1, (2 * device_cu_count() + tiles - 1) / tiles);
+    splits = std::min<int64_t>(splits, std::max<int64_t>(1, std::min<int64_t>(s / 128, part_cap / (s * R))));
+    int64_t ks = (s + splits - 1) / splits;
+    ks = (ks + 31) / 32 * 32;
+    const int nsplit = (int)((s + ks - 1) / ks);
+    g.k_split = ks;
+    g.c = plain(part, R);
+    g.c_zstride = s * R;
+    TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
+    TK_HIP(tk_sum_splits_f32p(part, nsplit, s * R, s * R, p.Z, r.st));
+}
+
 // Rayleigh-Ritz step closing an oversampled cold start (Rc = p.Rc[n] > R columns): with U (s x Rc,
 // orthonormal) in U64[n], B = U^T S U (Rc x Rc) is diagonalised in FP64 (block Jacobi) and the
 // factor becomes U V_R (s x R), V_R the eigenvectors of the R largest Ritz values, descending.  U V_R
@@ -953,8 +984,11 @@ void orth_iter(Run& r, int n, int q, bool cold) {
         TK_HIP(hipStreamSynchronize(r.st));
         snorm = std::sqrt(snorm);
     }
+    // reduced-precision sweeps: the warm step's S U from the FP32 copy of S that their Gram wrote
+    const bool su32 = r.lp_su && !cold && tol <= 0.0 && p.S32;
     for (int it = 0; it < q || (tol > 0.0 && it == q); ++it) {
-        su_product(r, n, R);
+        if (su32) su_product_f32(r, n, R);
+        else su_product(r, n, R);
         if (tol > 0.0 && !(cold && it == 0)) {
             resid = subspace_residual(r, p.U64[n], s, R) / std::max(snorm, 1e-300);
             if (resid <= tol || it == q) break;
@@ -1628,11 +1662,16 @@ void lp_gram(Run& r, Desc y, int64_t srows, int64_t K, int stage) {
         TK_HIP(lp_launch(g, p.ip, MK, LP_F32OUT, r.st));
     }
     StageTimer t(r, stage >= 0 ? TUCKER_STAGE_REDUCE : -1);
-    TK_HIP(gram_reduce(p.Pf, nsplit, srows, srows * srows, nullptr, p.S64, r.st));
+    TK_HIP(gram_reduce(p.Pf, nsplit, srows, srows * srows, r.lp_su ? p.S32 : nullptr, p.S64, r.st));
 }
 
 void sweep_tree_lp(Run& r) {
     Plan& p = r.p;
+    struct LpSu {
+        Run& r;
+        explicit LpSu(Run& run) : r(run) { r.lp_su = true; }
+        ~LpSu() { r.lp_su = false; }
+    } lp_su_scope(r);
     const int64_t s0 = p.s[0], s1 = p.s[1], s2 = p.s[2], s3 = p.s[3];
     const int64_t R0 = p.R[0], R1 = p.R[1], R2 = p.R[2], R3 = p.R[3];
     const int64_t R23p = p.R23p, L = s2 * s3;
