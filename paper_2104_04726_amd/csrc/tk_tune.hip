@@ -4,7 +4,9 @@
 // call of a key in the process fixes its choice for the rest of the process: when tuning is on for the
 // calling thread (tucker_options.autotune) and the stream is not being captured into a graph, every
 // candidate is launched twice on the caller's stream, the second launch timed with HIP events, and the
-// fastest is kept; otherwise the heuristic choice is kept.  Every later call with the same key reuses
+// fastest is kept unless the heuristic choice is within kTieMargin of it (near ties, whose order the
+// timing noise decides, then give the same choice in every process); otherwise the heuristic choice
+// is kept.  Every later call with the same key reuses
 // it, so within a process a shape's results do not depend on which calls ran before or beside it.
 // Candidates of one key must leave identical results or results of one fixed reduction order each,
 // and their outputs must be idempotent (stores, not accumulations).  tune_force overrides the choice
@@ -33,6 +35,7 @@ std::mutex g_mu;
 std::map<Key, Entry> g_table;
 thread_local bool t_enabled = false;
 constexpr int kMaxOp = 4;
+constexpr double kTieMargin = 0.03;   // the heuristic choice stands unless another is 3% faster
 std::atomic<int> g_force[kMaxOp] = {-1, -1, -1, -1};
 
 }  // namespace
@@ -98,6 +101,8 @@ int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStr
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (*err != hipSuccess) return heuristic;
+    if (heuristic >= 0 && heuristic < ncand && en.ms[heuristic] >= 0.0 && en.ms[heuristic] <= best * (1.0 + kTieMargin))
+        en.choice = heuristic;
     return keep(en);
 }
 
