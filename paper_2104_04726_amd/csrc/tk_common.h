@@ -192,8 +192,8 @@ enum TuneOp { kTuneF32Tile = 1, kTuneGramSplit = 2, kTuneLpTile = 3 };
 void tune_set_enabled(bool on);     // this thread's calls may time new keys
 bool tune_enabled();
 // The cached choice for (op, device, shape), else, when tuning is enabled and the stream is not
-// capturing, candidates 0..ncand-1 launched (twice each, the second timed) and the fastest cached;
-// otherwise `heuristic`.  launch(c) enqueues candidate c on s.
+// capturing, candidates 0..ncand-1 launched (three times each, the last two timed) and the fastest
+// cached unless `heuristic` is within the operation's tie margin of it; otherwise `heuristic`.  launch(c) enqueues candidate c on s.
 int tune_choose(int op, const int64_t shape[5], int ncand, int heuristic, hipStream_t s,
                 const std::function<hipError_t(int)>& launch, hipError_t* err);
 std::string tune_dump();
