@@ -464,6 +464,8 @@ struct Run {
     int rr_sweeps = 0;          // block-Jacobi sweeps of the Rayleigh-Ritz steps (oversampled starts)
     bool defer_ritz = false;    // an oversampled cold start leaves its Rayleigh-Ritz step to the caller
     bool lp_su = false;         // reduced-precision sweep: warm S U from the FP32 copy of S
+    double* fit0_slot = nullptr;  // set: the start's fit is still to be written here, by the first
+                                  // sweep's mode-1 update (its W = Y0 x_1 U1^T is the start's core)
 
     long long spin() const { return (long long)ctx->opt.wait_spin_limit; }
     double inner_tol() const { return ctx->opt.inner_tol; }
@@ -1086,6 +1088,13 @@ void direct_update(Run& r, const float* Y, int64_t A, int64_t s, int64_t B, int 
         } else {
             g.c = plain(W, wp.N);
             TK_HIP(gemm_f32(g, KM, KM, EPI_STORE, false, r.st));
+        }
+        if (n == 0 && r.fit0_slot) {
+            // first sweep, mode 1: Y0 = X x_2 U2^T x_3 U3^T x_4 U4^T with the start's factors and U1 not
+            // yet updated, so W = Y0 x_1 U1^T is the start's core and ||W|| gives the start's fit
+            TK_HIP(sumsq_f32(W, wp.R * wp.N, p.red, kSumsqBlocks, p.scal + 1, r.st));
+            TK_HIP(fit_from_norms(p.scal + 0, p.scal + 1, r.fit0_slot, r.st));
+            r.fit0_slot = nullptr;
         }
         // Z(m = i, n = r) = sum_(a,b) Y[a][i][b] W(k = (a, b), r) on the FP32 matrix cores, K split to
         // fill the chip and to at most kZSplitK per split; FP32 partials summed in FP64 into Z
@@ -2304,8 +2313,21 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
                 core_norm_and_fit(r, slot);
             }
         };
-        if (init_factors || ctx->opt.start != TUCKER_START_STHOSVD) core_from_x(r);   // (ST-HOSVD ends with G)
-        sweep_fit(p.fits + 0);
+        const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0 &&
+                            !(r.inner_tol() > 0.0) && !p.pp;
+        // The start's core is needed only for its fit when sweeps follow.  In an FP32 tree sweep the
+        // first mode-1 update forms W = Y0 x_1 U1^T from the start's factors, which is that core, so the
+        // start's fit is taken from W there instead of from two more products over X (ST-HOSVD ends with
+        // its core anyway).
+        const bool fit0_from_w = max_iters > 0 && p.prec == 0 && p.tree && !exact_fits &&
+                                 p.kind[0] != FIXED && direct_update_ok(r, 0) &&
+                                 (init_factors || ctx->opt.start != TUCKER_START_STHOSVD);
+        if (fit0_from_w) {
+            r.fit0_slot = p.fits + 0;
+        } else {
+            if (init_factors || ctx->opt.start != TUCKER_START_STHOSVD) core_from_x(r);   // (ST-HOSVD ends with G)
+            sweep_fit(p.fits + 0);
+        }
         TK_HIP(hipEventRecord(ctx->ev[1], s));
         int done = 0;
         std::vector<double> hf(2);
@@ -2321,30 +2343,33 @@ tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim
             else
                 sweep_generic(r);
         };
-        // Graph replay: one sweep (and its fit) is captured from the stream once and replayed
-        // max_iters times; every node reads and writes the same workspace each sweep, and the fit
-        // lands in fits[k] through a device-side counter.  Needs a capturable (non-null) stream,
-        // no per-sweep host read (tol = 0) and no stage timers.
-        const bool graphs = ctx->opt.use_graphs && s != nullptr && !ctx->opt.timing && !(tol > 0.0) && max_iters > 0 &&
-                            !(r.inner_tol() > 0.0) && !p.pp;
+        // Graph replay: the first sweep runs on the stream directly (in an FP32 tree sweep it also
+        // leaves the start's fit); the next sweep (and its fit) is captured from the stream once and
+        // replayed for sweeps 2 .. max_iters; every node reads and writes the same workspace each
+        // sweep, and the fit lands in fits[k] through a device-side counter.  Needs a capturable
+        // (non-null) stream, no per-sweep host read (tol = 0) and no stage timers.
         GraphHold hold{s};
         if (graphs) {
-            TK_HIP(tk_set_int(p.shifts + 3, 1, s));
-            TK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-            try {
-                one_sweep();
-                core_norm_and_fit(r, p.scal + 4);
-                TK_HIP(tk_fit_push(p.scal + 4, p.shifts + 3, p.fits, s));
-            } catch (...) {
-                hipGraph_t g2 = nullptr;
-                (void)hipStreamEndCapture(s, &g2);
-                if (g2) (void)hipGraphDestroy(g2);
-                (void)hipGetLastError();
-                throw;
+            one_sweep();
+            sweep_fit(p.fits + 1);
+            if (max_iters > 1) {
+                TK_HIP(tk_set_int(p.shifts + 3, 2, s));
+                TK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+                try {
+                    one_sweep();
+                    core_norm_and_fit(r, p.scal + 4);
+                    TK_HIP(tk_fit_push(p.scal + 4, p.shifts + 3, p.fits, s));
+                } catch (...) {
+                    hipGraph_t g2 = nullptr;
+                    (void)hipStreamEndCapture(s, &g2);
+                    if (g2) (void)hipGraphDestroy(g2);
+                    (void)hipGetLastError();
+                    throw;
+                }
+                TK_HIP(hipStreamEndCapture(s, &hold.graph));
+                TK_HIP(hipGraphInstantiate(&hold.exec, hold.graph, nullptr, nullptr, 0));
+                for (int k = 2; k <= max_iters; ++k) TK_HIP(hipGraphLaunch(hold.exec, s));
             }
-            TK_HIP(hipStreamEndCapture(s, &hold.graph));
-            TK_HIP(hipGraphInstantiate(&hold.exec, hold.graph, nullptr, nullptr, 0));
-            for (int k = 1; k <= max_iters; ++k) TK_HIP(hipGraphLaunch(hold.exec, s));
             done = max_iters;
         }
         // pairwise perturbation: ordinary sweeps until the factors settle, then perturbation sweeps
