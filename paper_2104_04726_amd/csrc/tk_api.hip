@@ -504,9 +504,12 @@ struct StageTimer {
 // out = in x_n U^T (contract, U: dims[n] x R)  or  in x_n U (expand, U: s x dims[n], result dim s)
 // dims: current dims of `in` (order N); the new size of mode n is newdim.
 // When resid_ref is set (only for an expanding GEMM), the product is not stored: the squared
-// difference against resid_ref (same layout as the product) is summed into rpart.
+// difference against resid_ref (same layout as the product) is summed into rpart.  Ut (optional, an
+// expanding product over an inner mode): U^T (dims[n] x newdim), read as the k-major operand, so that
+// both operands take 16-byte vector loads.
 void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float* U, int64_t newdim,
-         bool expand, float* out, const float* resid_ref = nullptr, int64_t* nblocks = nullptr) {
+         bool expand, float* out, const float* resid_ref = nullptr, int64_t* nblocks = nullptr,
+         const float* Ut = nullptr) {
     const int64_t A = prod(dims, 0, n), K = dims[n], B = prod(dims, n + 1, N);
     const int64_t R = newdim;
     if (!resid_ref && K <= kSmallMode && R <= kSmallMode) {
@@ -540,6 +543,9 @@ void ttm(Run& r, const float* in, const int64_t* dims, int N, int n, const float
         g.K = K;
         if (!expand) {
             g.a = plain(U, R);   // A(m=r, k) = U[k][r]
+            oa = KM;
+        } else if (Ut) {
+            g.a = plain(Ut, R);  // A(m=i, k=r) = Ut[r][i]
             oa = KM;
         } else {
             g.a = plain(U, K);   // A(m=i, k=r) = U[i][r]
@@ -1789,12 +1795,19 @@ void expand_chain(Run& r, const float* G, float* const* U, float* out, const flo
         int64_t d[3] = {R0, R1, s2 * s3};
         ttm(r, p.T12, d, 3, 1, U[1], p.s[1], true, p.T1);
         d[1] = p.s[1];
+        // the last product, the chain's largest, reads U1 through its transpose, kept in p.P (the Gram
+        // partials and one-step W products that use p.P are consumed before any reconstruction)
+        float* u0t = nullptr;
+        if (p.P && p.s[0] * R0 <= 2 * p.P_elems) {
+            u0t = reinterpret_cast<float*>(p.P);
+            TK_HIP(transpose_f32(U[0], p.s[0], R0, u0t, r.st));
+        }
         if (Xref) {
             int64_t nb = 0;
-            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, nullptr, Xref, &nb);
+            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, nullptr, Xref, &nb, u0t);
             TK_HIP(reduce_f64(p.rpart, nb, p.scal + 2, r.st));
         } else {
-            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, out);
+            ttm(r, p.T1, d, 3, 0, U[0], p.s[0], true, out, nullptr, nullptr, u0t);
         }
         return;
     }

@@ -231,6 +231,8 @@ hipError_t ns_step(const double* B, double* D, int64_t n, hipStream_t s);
 // r eigenvectors (descending) to U64 (n x r fp64) and U32 (n x r fp32, nullable), all
 // eigenvalues descending to lam (nullable).  Vio (nullable, n x n): receives the whole sorted
 // eigenvector basis; with warm, it also supplies the starting basis (a previous result).
+// out (cols x rows) = in^T, in row-major FP32 (rows x cols)
+hipError_t transpose_f32(const float* in, int64_t rows, int64_t cols, float* out, hipStream_t s);
 hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam,
                       hipStream_t s, double* Vio = nullptr, bool warm = false);
 

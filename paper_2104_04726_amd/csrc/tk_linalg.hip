@@ -764,6 +764,31 @@ hipError_t finish_factor(const int* need, const double* Q1, double* U64, float* 
     return hipGetLastError();
 }
 
+// out (cols x rows) = in^T for a row-major FP32 in (rows x cols), through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ in, int64_t rows, int64_t cols,
+                                                            float* __restrict__ out) {
+    __shared__ float t[32][33];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) t[k][tx] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (c < cols && r < rows) out[c * rows + r] = t[tx][k];
+    }
+}
+
+hipError_t transpose_f32(const float* in, int64_t rows, int64_t cols, float* out, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if ((rows + 31) / 32 > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(256), 0, s, in, rows, cols, out);
+    return hipGetLastError();
+}
+
 hipError_t jacobi_eig(const double* S, int n, int r, double* U64, float* U32, double* lam, hipStream_t s,
                       double* Vio, bool warm) {
     if (n < 1 || n > 64 || r < 1 || r > n) return hipErrorInvalidValue;
