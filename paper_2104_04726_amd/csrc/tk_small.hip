@@ -395,63 +395,67 @@ __global__ __launch_bounds__(256) void pair_ttm_fixed(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------- fibre Gram (L <= 64)
-// Each block accumulates the lower triangle of sum_a x_a x_a^T over its share of fibres,
-// staged through LDS 64 fibres at a time; thread -> fixed set of (i,j) pairs.
-constexpr int kFG_FPB = 64;
+// F = sum_f x_f x_f^T over the fibres x_f (rows of length L <= 64) is a Gram with a long contraction
+// (the fibre index), run on the FP64 matrix cores: the L columns are covered by NB blocks of 16, and
+// each wave accumulates the NB (NB + 1) / 2 lower 16 x 16 blocks over groups of 4 fibres
+// (v_mfma_f64_16x16x4: lane l holds x_(f0 + l/16)[16 I + l%16] as the A operand of block row I and as
+// the B operand of block column J).  Products of FP32 values are exact in FP64.  The fibre groups go
+// to the waves round-robin; the four waves of a block add their sums in wave order in LDS, and the
+// block writes its lower triangle as one partial.
+typedef double f64x4_fg __attribute__((ext_vector_type(4)));
+template <int NB>
 __global__ __launch_bounds__(256) void fibre_gram_kernel(const float* __restrict__ in, int64_t A, int L,
                                                          double* __restrict__ partial) {
-    // F = sum_f x_f x_f^T over the fibres x_f (rows of length L <= 64) of this block's chunks.
-    // Thread = one 3 x 3 tile (I, J), I >= J, of the lower triangle and one phase h of the fibres
-    // (fibres h, h + H, ... of each chunk); the H phase sums are added in phase order at the end.
-    constexpr int LDX = 67;                       // LDS row stride (L padded to a multiple of 3)
-    __shared__ float xs[kFG_FPB * LDX];
-    __shared__ double red[9 * 256];
-    const int t = threadIdx.x;
-    const int bL = (L + 2) / 3, Lp = 3 * bL;
-    const int P = bL * (bL + 1) / 2;
-    const int H = max(1, min(16, 256 / P));
-    const bool active = t < P * H;
-    const int pidx = active ? t % P : 0, ph = active ? t / P : 0;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
-    const int J = pidx - I * (I + 1) / 2;
-    double acc[9];
+    constexpr int NT = NB * (NB + 1) / 2, LD = 16 * NB, UNR = 4;
+    __shared__ double red[LD * LD];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kk = lane >> 4;
+    f64x4_fg acc[NT];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) acc[u] = 0.0;
-    const int64_t nchunks = (A + kFG_FPB - 1) / kFG_FPB;
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t f0 = ch * kFG_FPB;
-        const int nf = (int)((A - f0) < kFG_FPB ? (A - f0) : kFG_FPB);
-        __syncthreads();
-        for (int g = t; g < kFG_FPB * Lp; g += blockDim.x) {
-            const int f = g / Lp, c = g - f * Lp;
-            xs[f * LDX + c] = (f < nf && c < L) ? in[(f0 + f) * L + c] : 0.f;
-        }
-        __syncthreads();
-        if (active) {
-            const float* xa = xs + 3 * I;
-            const float* xb = xs + 3 * J;
-            for (int f = ph; f < nf; f += H) {
-                const double a0 = xa[f * LDX], a1 = xa[f * LDX + 1], a2 = xa[f * LDX + 2];
-                const double b0 = xb[f * LDX], b1 = xb[f * LDX + 1], b2 = xb[f * LDX + 2];
-                // products of FP32 values are exact in FP64
-                acc[0] = fma(a0, b0, acc[0]); acc[1] = fma(a0, b1, acc[1]); acc[2] = fma(a0, b2, acc[2]);
-                acc[3] = fma(a1, b0, acc[3]); acc[4] = fma(a1, b1, acc[4]); acc[5] = fma(a1, b2, acc[5]);
-                acc[6] = fma(a2, b0, acc[6]); acc[7] = fma(a2, b1, acc[7]); acc[8] = fma(a2, b2, acc[8]);
+    for (int t = 0; t < NT; ++t) acc[t] = f64x4_fg{0.0, 0.0, 0.0, 0.0};
+    const int64_t ngroups = (A + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    for (int64_t g0 = (int64_t)blockIdx.x * 4 + wave; g0 < ngroups; g0 += stride * UNR) {
+        double xv[UNR][NB];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t f = (g0 + u * stride) * 4 + kk;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int c = 16 * b + r;
+                xv[u][b] = (f < A && c < L) ? (double)in[f * L + c] : 0.0;
             }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < 9; ++u) red[u * 256 + t] = acc[u];
-    __syncthreads();
-    if (t < P) {
-        double* dst = partial + (int64_t)blockIdx.x * L * L;
-        for (int u = 0; u < 9; ++u) {
-            double v = 0.0;
-            for (int h = 0; h < H; ++h) v += red[u * 256 + h * P + t];
-            const int i = 3 * I + u / 3, j = 3 * J + u % 3;
-            if (i < L && j <= i) dst[i * L + j] = v;
+        for (int u = 0; u < UNR; ++u) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][I], xv[u][J], acc[t], 0, 0, 0);
         }
+    }
+    // lane l holds rows l/16 + 4 v, column l % 16 of each block
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J, ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int idx = (16 * I + kk + 4 * v) * LD + 16 * J + r;
+                        red[idx] = (w == 0 ? 0.0 : red[idx]) + acc[t][v];
+                    }
+        }
+        __syncthreads();
+    }
+    double* dst = partial + (int64_t)blockIdx.x * L * L;
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+        const int i = e / L, j = e - (e / L) * L;
+        if (j <= i) dst[i * L + j] = red[i * LD + j];
     }
 }
 
@@ -789,7 +793,11 @@ hipError_t pair_ttm(const float* in, int64_t A, int p, int q, const float* U3, i
 hipError_t fibre_gram(const float* in, int64_t A, int L, double* partial, int nblocks, double* F,
                       hipStream_t s) {
     if (L < 1 || L > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fibre_gram_kernel, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
+    const int nb = (L + 15) / 16;
+    if (nb == 1) hipLaunchKernelGGL(fibre_gram_kernel<1>, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
+    else if (nb == 2) hipLaunchKernelGGL(fibre_gram_kernel<2>, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
+    else if (nb == 3) hipLaunchKernelGGL(fibre_gram_kernel<3>, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
+    else hipLaunchKernelGGL(fibre_gram_kernel<4>, dim3(nblocks), dim3(256), 0, s, in, A, L, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fibre_gram_reduce, dim3((unsigned)((L * (L + 1) / 2 * 32 + 255) / 256)), dim3(256), 0, s,
