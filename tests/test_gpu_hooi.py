@@ -92,6 +92,7 @@ def test_tiny_exact_rank_recovery(ctx):
     ((8, 7, 6, 5, 4), (3, 3, 2, 2, 2), 5),        # order 5, small modes
     ((130, 70, 5, 4), (12, 10, 3, 2), 5),         # order 4 tree with one large mode
     ((96, 80, 2, 9), (20, 16, 2, 5), 5),          # tree, R3 = s3
+    ((100, 72, 4, 14), (12, 10, 3, 5), 5),        # tree, 56-long fibres: four 16-blocks in the fibre Gram
 ])
 def test_exact_rank_orders(ctx, dims, ranks, iters):
     x, _, _ = make_exact_rank(dims, ranks, seed=3, noise_rel=1e-3)
