@@ -94,9 +94,10 @@ typedef struct {
                                     (checked on the host after every step, so sweeps are then
                                     launched one kernel at a time); steps taken are reported in
                                     tucker_stats                                               */
-    int use_graphs;              /* 1: capture one sweep as a HIP graph and replay it for every
-                                    sweep (needs a non-NULL stream, timing 0 and tol 0; otherwise
-                                    the sweeps are launched one kernel at a time)              */
+    int use_graphs;              /* 1: run the first sweep directly, capture the second as a HIP
+                                    graph and replay it for every later sweep (needs a non-NULL
+                                    stream, timing 0 and tol 0; otherwise the sweeps are launched
+                                    one kernel at a time).  Results equal the direct launches'. */
     size_t hbm_budget_bytes;     /* workspace cap; 0 = no cap                                 */
     uint64_t seed;               /* seed of the cold-start basis (counter-based generator)    */
     int timing;                  /* 1: time the sweep stages with HIP events (tucker_stats).
@@ -235,7 +236,10 @@ tucker_status tucker_decompose(tucker_ctx* ctx, const float* tensor, int ndim,
  *   init_factors host array of ndim device pointers (nullable): orthonormal s_n x R_n starting
  *                factors used instead of the T-HOSVD (resume / refinement).
  *   fit_history  host, nullable, max_iters + 1 doubles: fit_0 (start) and the fit after each
- *                sweep (as described for tol); entries past sweeps_done are left untouched. */
+ *                sweep (as described for tol); entries past sweeps_done are left untouched.
+ *                With tol = 0, FP32 and an order-4 image-stack shape, fit_0 is taken from the
+ *                first sweep's product Y x_1 U1^T, which is the start's core (eq. (1)), instead
+ *                of from a separate pass over X: the same quantity in another rounding order. */
 tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim,
                                   const int64_t* dims, const int64_t* ranks,
                                   int max_iters, double tol,
