@@ -237,8 +237,9 @@ tucker_status tucker_decompose(tucker_ctx* ctx, const float* tensor, int ndim,
  *                factors used instead of the T-HOSVD (resume / refinement).
  *   fit_history  host, nullable, max_iters + 1 doubles: fit_0 (start) and the fit after each
  *                sweep (as described for tol); entries past sweeps_done are left untouched.
- *                With tol = 0, FP32, a T-HOSVD start and the dimension-tree path (order 4, the
- *                last two modes 64 elements or fewer together, modes 1 and 2 large), fit_0 is taken
+ *                With tol = 0, FP32, a T-HOSVD start (or init_factors) and the dimension-tree path
+ *                (order 4, the last two modes 64 elements or fewer together, mode 1 above 64 with
+ *                one step per update), fit_0 is taken
  *                from the first sweep's product Y x_1 U1^T, which is the start's core, instead of
  *                from a separate pass over X: the same quantity in another rounding order. */
 tucker_status tucker_decompose_ex(tucker_ctx* ctx, const float* tensor, int ndim,
