@@ -115,7 +115,8 @@ typedef struct {
                                     count) are measured on the device
                                     on first use and the fastest kept, unless the built-in
                                     heuristic's choice is within 3% of it (10% for the Gram split
-                                    count, whose candidates round differently) (tucker_autotune_dump);
+                                    count, whose candidates round differently, and for the
+                                    reduced-precision LDS staging) (tucker_autotune_dump);
                                     0: such choices take the built-in heuristic.  Either way the
                                     first call of a shape fixes its choice for the process.     */
     double pp_tol;               /* > 0: pairwise-perturbation sweeps (Sec. III-B, eq. (9)-(13)).
